@@ -1,0 +1,231 @@
+/*
+ * qsv.h - C ABI of the MI355X (gfx950) state-vector engine for parameterized circuits.
+ *
+ * The engine holds a 2^n complex amplitude vector in device memory (HBM), applies
+ * 1- and 2-qubit gates and fused gate blocks to it, reduces Pauli-sum expectations,
+ * and computes adjoint-method gradients of those expectations with respect to the
+ * circuit parameters (MindSpore Quantum, arXiv 2406.17248: section 2.3 for the gates,
+ * section 2.5 for Pauli-sum observables, section 2.6 for the simulator's apply / get
+ * semantics, section 4.1 for the gradient API, section 7 (QAOA task) for the adjoint
+ * method).
+ *
+ * Conventions
+ *  - Little-endian basis order: bit q of an amplitude's index is qubit q (section 2.6).
+ *  - Amplitudes are interleaved (re, im): float2 for QSV_C64, double2 for QSV_C128.
+ *  - Every number crossing the ABI (angles, matrices, coefficients, expectations,
+ *    gradients) is fp64.  For QSV_C64 the library forms gate matrices in fp64 and rounds
+ *    them to fp32 once per call; all reductions accumulate in fp64 in a fixed order, so
+ *    results are bitwise repeatable for the same inputs and options.
+ *  - Return value: QSV_OK (0) on success, a negative QSV_E* code otherwise.  On error
+ *    qsv_last_error() returns a message for the calling thread.  No C++ exception
+ *    crosses the ABI.  Arguments are validated before any device work is queued; an
+ *    invalid call leaves the state unchanged.
+ *  - Ownership: every host array passed in is owned by the caller and may be freed when
+ *    the call returns (the library copies what it needs).  A state from
+ *    qsv_state_create owns its device buffer; a wrapped state does not.
+ *  - Threading: a qsv_state is not thread-safe; calls on one state must not overlap.
+ *    Work is queued on the state's stream (default: the null stream); calls that
+ *    return host values (expectations, gradients, qsv_state_get) synchronize it.
+ */
+#ifndef QSV_H
+#define QSV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------ */
+#define QSV_OK       0
+#define QSV_EINVAL  -1  /* bad argument: qubit out of range, duplicate targets, control on a
+                           target, parameter index >= n_params, size mismatch, null pointer */
+#define QSV_ENOMEM  -2  /* device or host allocation failed */
+#define QSV_EDTYPE  -3  /* unknown dtype, or dtype mismatch between two states */
+#define QSV_EHIP    -4  /* a HIP runtime call failed (message in qsv_last_error) */
+#define QSV_ERANGE  -5  /* size beyond the supported maximum (n_qubits > 34, too many params) */
+#define QSV_ENOTSUP -6  /* valid request the engine does not implement (e.g. the two-term
+                           parameter shift of a controlled rotation) */
+
+/* ---- amplitude types --------------------------------------------------------------- */
+typedef enum { QSV_C64 = 0, QSV_C128 = 1 } qsv_dtype;
+
+/* ---- gate kinds (section 2.3) ---------------------------------------------------------
+ * Fixed: X, Y, Z, H as printed in section 2.3; S = diag(1, i), SDG = S^dag,
+ * T = diag(1, e^{i pi/4}), TDG = T^dag, SWAP.
+ * Rotations (one angle): RX, RY, RZ = exp(-i theta P / 2) (section 2.3);
+ * RXX, RYY, RZZ = exp(-i theta P(x)P / 2) on targets[0], targets[1];
+ * PS (phase shift) = diag(1, e^{i theta}).
+ * U3 (three angles theta, phi, lambda) = [[cos t/2, -e^{i l} sin t/2],
+ *                                         [e^{i p} sin t/2, e^{i(p+l)} cos t/2]],
+ * which equals the section 4.1 rotation RZ(phi) RY(theta) RZ(lambda) up to a global phase.
+ * MAT1 / MAT2: explicit 2x2 / 4x4 complex matrix (section 2.3, custom gates).
+ * Any kind may carry controls (ctrl_mask); CNOT is X with one control, CZ is Z with one
+ * control.  For 2-qubit kinds, bit b of a matrix row/column index refers to targets[b]. */
+enum qsv_gate_kind {
+  QSV_GATE_X = 0, QSV_GATE_Y = 1, QSV_GATE_Z = 2, QSV_GATE_H = 3,
+  QSV_GATE_S = 4, QSV_GATE_SDG = 5, QSV_GATE_T = 6, QSV_GATE_TDG = 7,
+  QSV_GATE_RX = 8, QSV_GATE_RY = 9, QSV_GATE_RZ = 10, QSV_GATE_PS = 11,
+  QSV_GATE_RXX = 12, QSV_GATE_RYY = 13, QSV_GATE_RZZ = 14, QSV_GATE_U3 = 15,
+  QSV_GATE_SWAP = 16, QSV_GATE_MAT1 = 17, QSV_GATE_MAT2 = 18,
+  QSV_GATE_KIND_COUNT = 19
+};
+
+/* One gate record.  Angle a of the gate is bound as
+ *     angle_a = angle_const[a] + param_coeff[a] * params[param_index[a]]
+ * (param_index[a] = -1: the constant alone), the linear parameter expressions of
+ * section 2.2.  Unused angle slots must have param_index = -1.  For 1-qubit kinds
+ * targets[1] is ignored.  matrix_offset indexes, in complex elements, the circuit's
+ * matrix array (MAT1: 4 row-major entries, MAT2: 16); ignored for other kinds.
+ * Layout (88 bytes): int32 kind; int32 targets[2]; int32 param_index[3];
+ * uint64 ctrl_mask; double param_coeff[3]; double angle_const[3]; int64 matrix_offset. */
+typedef struct qsv_gate {
+  int32_t  kind;
+  int32_t  targets[2];
+  int32_t  param_index[3];
+  uint64_t ctrl_mask;
+  double   param_coeff[3];
+  double   angle_const[3];
+  int64_t  matrix_offset;
+} qsv_gate;
+
+/* A circuit: gates applied in array order (section 2.4).  matrices: interleaved
+ * (re, im) fp64, n_matrix_doubles entries (may be NULL when no MAT gate is used). */
+typedef struct qsv_circuit {
+  int32_t          n_qubits;
+  int32_t          reserved;
+  const qsv_gate*  gates;
+  size_t           n_gates;
+  const double*    matrices;
+  size_t           n_matrix_doubles;
+} qsv_circuit;
+
+/* A Pauli sum H = sum_k coeffs[k] P_k (section 2.5).  P_k is the tensor product with X
+ * on qubits set only in x_masks[k], Z on qubits set only in z_masks[k], Y on qubits set
+ * in both, identity elsewhere; so P_k|x> = i^{popcount(x_k & z_k)} (-1)^{popcount(x & z_k)}
+ * |x xor x_k>.  Coefficients are real, so H is Hermitian. */
+typedef struct qsv_pauli_sum {
+  size_t          n_terms;
+  const double*   coeffs;
+  const uint64_t* x_masks;
+  const uint64_t* z_masks;
+} qsv_pauli_sum;
+
+typedef struct qsv_state qsv_state;
+
+/* ---- errors -------------------------------------------------------------------------- */
+const char* qsv_status_string(int status);
+/* Message of the last failed call on this thread ("" if none). */
+const char* qsv_last_error(void);
+/* Library version string. */
+const char* qsv_version(void);
+
+/* ---- states (section 2.6: Simulator('mqvector', n), get_qs / set_qs / reset) --------- */
+/* Allocate a 2^n_qubits state on the current HIP device, set to |0...0>.
+ * 1 <= n_qubits <= 34.  *out receives the handle (QSV_ENOMEM if HBM is short). */
+int qsv_state_create(int32_t n_qubits, int32_t dtype, qsv_state** out);
+/* Wrap caller-owned device memory holding 2^n_qubits amplitudes of the given dtype
+ * (e.g. a torch tensor).  Contents are used as they are; the caller keeps the memory
+ * alive until qsv_state_destroy. */
+int qsv_state_wrap(void* device_ptr, int32_t n_qubits, int32_t dtype, qsv_state** out);
+/* Free the state, its workspaces and (if owned) its amplitude buffer.  NULL is a no-op. */
+int qsv_state_destroy(qsv_state* s);
+/* Queue all further work of this state on the given hipStream_t (NULL: null stream). */
+int qsv_state_set_stream(qsv_state* s, void* hip_stream);
+/* Wait for all queued work of this state. */
+int qsv_state_synchronize(qsv_state* s);
+/* Basic queries. */
+int qsv_state_info(const qsv_state* s, int32_t* n_qubits, int32_t* dtype, void** device_ptr);
+/* Set the state to |0...0> (section 2.6, reset). */
+int qsv_state_reset(qsv_state* s);
+/* Copy n_amps = 2^n host amplitudes of the state's dtype into the state (set_qs). */
+int qsv_state_set(qsv_state* s, const void* host_amps, size_t n_amps);
+/* Copy the state to n_amps = 2^n host amplitudes of its dtype (get_qs). */
+int qsv_state_get(qsv_state* s, void* host_amps, size_t n_amps);
+/* Copy the amplitudes of src into dst (same n and dtype). */
+int qsv_state_copy(qsv_state* dst, const qsv_state* src);
+
+/* Execution options (integers).  Defaults are chosen per dtype and n. */
+enum qsv_option {
+  QSV_OPT_TILE_QUBITS = 0,   /* qubits per fused LDS tile pass (0: per-gate kernels only);
+                                default 13 (c64) / 12 (c128); clamped to n */
+  QSV_OPT_ADJ_TILE_QUBITS = 1, /* tile width of the adjoint reverse sweep (psi and lambda
+                                  share LDS); default 12 (c64) / 11 (c128) */
+  QSV_OPT_THREADS = 2,       /* reserved (threads per tile workgroup follow the tile width) */
+  QSV_OPT_PROFILE = 3,       /* 1: time every kernel launch with HIP events on the state's
+                                stream (read with qsv_profile_read); 0: off (default) */
+  QSV_OPT_COUNT = 4
+};
+int qsv_state_set_option(qsv_state* s, int32_t option, int64_t value);
+int qsv_state_get_option(const qsv_state* s, int32_t option, int64_t* value);
+
+/* ---- hot path ------------------------------------------------------------------------ */
+/* psi <- U(params) psi (section 2.6, apply_circuit).  n_params must cover every
+ * param_index used.  The circuit's n_qubits must equal the state's. */
+int qsv_apply_circuit(qsv_state* s, const qsv_circuit* c, const double* params, size_t n_params);
+
+/* <psi|H|psi> (section 2.6, get_expectation with U_l = U_r = I); the state is unchanged.
+ * *out_im is the rounding-level imaginary part (H is Hermitian); either pointer may be NULL. */
+int qsv_expectation(qsv_state* s, const qsv_pauli_sum* h, double* out_re, double* out_im);
+
+/* dst <- H src, unnormalized (section 2.6, apply_hamiltonian); dst != src, same n/dtype. */
+int qsv_apply_pauli_sum(qsv_state* dst, const qsv_state* src, const qsv_pauli_sum* h);
+
+/* E(params) = <psi0|U^dag H U|psi0> and dE/dparams by the adjoint method (section 4.1,
+ * get_expectation_with_grad; section 7, adjoint method), starting from the state's
+ * current contents psi0, which are left unchanged.  out_grad has n_params entries;
+ * parameters not used by the circuit get 0.  Every parameterized gate kind is
+ * supported, with or without controls. */
+int qsv_expectation_and_grad(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h,
+                             const double* params, size_t n_params,
+                             double* out_E, double* out_grad);
+
+/* The same for a batch of parameter sets sharing the start state and circuit structure
+ * (section 4.1: outputs [n_batch] and [n_batch][n_params] with one Hamiltonian).
+ * params is row-major [batch][n_params]; out_E[batch]; out_grad[batch][n_params]. */
+int qsv_expectation_and_grad_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h,
+                                   const double* params, size_t batch, size_t n_params,
+                                   double* out_E, double* out_grad);
+
+/* Energies only, for a batch of parameter sets: out_E[batch] (no gradient). */
+int qsv_expectation_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h,
+                          const double* params, size_t batch, size_t n_params, double* out_E);
+
+/* Gradient by the two-term parameter-shift rule, evaluated on the GPU with the same
+ * kernels (2 energies per parameterized angle occurrence).  Comparator for the adjoint
+ * method.  QSV_ENOTSUP if a parameterized gate has controls. */
+int qsv_param_shift_grad_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h,
+                               const double* params, size_t batch, size_t n_params,
+                               double* out_E, double* out_grad);
+
+/* ---- profiling ----------------------------------------------------------------------- */
+/* Kernel classes timed when QSV_OPT_PROFILE is 1. */
+enum qsv_kernel_class {
+  QSV_K_TILE_FORWARD = 0,   /* fused forward tile passes */
+  QSV_K_TILE_ADJOINT = 1,   /* fused adjoint reverse-sweep passes (psi and lambda) */
+  QSV_K_PAULI = 2,          /* Pauli-sum passes (expectation, lambda = H psi) */
+  QSV_K_GATE_STREAM = 3,    /* unfused per-gate passes */
+  QSV_K_OTHER = 4,          /* state init, broadcast, reductions */
+  QSV_K_COUNT = 5
+};
+/* Synchronize the state's stream and return, for one kernel class, the summed device
+ * time (ms) of the launches recorded since the last read, their number, and the
+ * algorithmic HBM bytes they move (each amplitude a launch must read or write, once).
+ * Reading clears the class's record.  Any output pointer may be NULL. */
+int qsv_profile_read(qsv_state* s, int32_t kernel_class, double* total_ms, int64_t* launches,
+                     double* algorithmic_bytes);
+
+/* ---- host-only diagnostics (no device work; usable without a GPU) ------------------- */
+/* Plan the fused execution of a circuit with tile width tile_qubits.  On return
+ * order[i] is the index of the i-th gate executed, pass_of[i] its tile pass, and
+ * *n_passes the number of passes; the arrays must hold n_gates entries.  tile_masks,
+ * when not NULL, receives up to max_passes 64-bit masks of each pass's tile qubits. */
+int qsv_plan_debug(const qsv_circuit* c, int32_t tile_qubits, int32_t* order, int32_t* pass_of,
+                   int32_t* n_passes, uint64_t* tile_masks, int32_t max_passes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSV_H */

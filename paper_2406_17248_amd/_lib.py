@@ -1,0 +1,388 @@
+"""ctypes binding of libqsv.so (the HIP state-vector engine).
+
+Argument marshalling only: every step of the hot path runs in the library's HIP
+kernels.  Loading fails loudly when the library has not been built; there is no CPU
+fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqsv.so")
+
+QSV_OK, QSV_EINVAL, QSV_ENOMEM, QSV_EDTYPE, QSV_EHIP, QSV_ERANGE, QSV_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+QSV_C64, QSV_C128 = 0, 1
+OPT_TILE_QUBITS, OPT_ADJ_TILE_QUBITS, OPT_THREADS, OPT_PROFILE = 0, 1, 2, 3
+K_TILE_FORWARD, K_TILE_ADJOINT, K_PAULI, K_GATE_STREAM, K_OTHER = 0, 1, 2, 3, 4
+
+GATE_KIND = {
+    "X": 0, "Y": 1, "Z": 2, "H": 3, "S": 4, "SDG": 5, "T": 6, "TDG": 7,
+    "RX": 8, "RY": 9, "RZ": 10, "PS": 11, "RXX": 12, "RYY": 13, "RZZ": 14, "U3": 15,
+    "SWAP": 16, "MAT1": 17, "MAT2": 18,
+}
+
+EXPORTED = (
+    "qsv_status_string", "qsv_last_error", "qsv_version",
+    "qsv_state_create", "qsv_state_wrap", "qsv_state_destroy", "qsv_state_set_stream",
+    "qsv_state_synchronize", "qsv_state_info", "qsv_state_reset", "qsv_state_set", "qsv_state_get",
+    "qsv_state_copy", "qsv_state_set_option", "qsv_state_get_option",
+    "qsv_apply_circuit", "qsv_expectation", "qsv_apply_pauli_sum",
+    "qsv_expectation_and_grad", "qsv_expectation_and_grad_batch", "qsv_expectation_batch",
+    "qsv_param_shift_grad_batch", "qsv_plan_debug", "qsv_profile_read",
+)
+
+
+class qsv_gate(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32),
+        ("targets", C.c_int32 * 2),
+        ("param_index", C.c_int32 * 3),
+        ("ctrl_mask", C.c_uint64),
+        ("param_coeff", C.c_double * 3),
+        ("angle_const", C.c_double * 3),
+        ("matrix_offset", C.c_int64),
+    ]
+
+
+class qsv_circuit(C.Structure):
+    _fields_ = [
+        ("n_qubits", C.c_int32),
+        ("reserved", C.c_int32),
+        ("gates", C.POINTER(qsv_gate)),
+        ("n_gates", C.c_size_t),
+        ("matrices", C.POINTER(C.c_double)),
+        ("n_matrix_doubles", C.c_size_t),
+    ]
+
+
+class qsv_pauli_sum(C.Structure):
+    _fields_ = [
+        ("n_terms", C.c_size_t),
+        ("coeffs", C.POINTER(C.c_double)),
+        ("x_masks", C.POINTER(C.c_uint64)),
+        ("z_masks", C.POINTER(C.c_uint64)),
+    ]
+
+
+assert C.sizeof(qsv_gate) == 88, "qsv_gate layout must match include/qsv.h"
+
+
+class QsvError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"qsv error {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libqsv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2406_17248_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, sz, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t, C.POINTER(C.c_double)
+        sigs = {
+            "qsv_status_string": ([C.c_int], C.c_char_p),
+            "qsv_last_error": ([], C.c_char_p),
+            "qsv_version": ([], C.c_char_p),
+            "qsv_state_create": ([i32, i32, C.POINTER(vp)], C.c_int),
+            "qsv_state_wrap": ([vp, i32, i32, C.POINTER(vp)], C.c_int),
+            "qsv_state_destroy": ([vp], C.c_int),
+            "qsv_state_set_stream": ([vp, vp], C.c_int),
+            "qsv_state_synchronize": ([vp], C.c_int),
+            "qsv_state_info": ([vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(vp)], C.c_int),
+            "qsv_state_reset": ([vp], C.c_int),
+            "qsv_state_set": ([vp, vp, sz], C.c_int),
+            "qsv_state_get": ([vp, vp, sz], C.c_int),
+            "qsv_state_copy": ([vp, vp], C.c_int),
+            "qsv_state_set_option": ([vp, i32, i64], C.c_int),
+            "qsv_state_get_option": ([vp, i32, C.POINTER(i64)], C.c_int),
+            "qsv_apply_circuit": ([vp, C.POINTER(qsv_circuit), dp, sz], C.c_int),
+            "qsv_expectation": ([vp, C.POINTER(qsv_pauli_sum), dp, dp], C.c_int),
+            "qsv_apply_pauli_sum": ([vp, vp, C.POINTER(qsv_pauli_sum)], C.c_int),
+            "qsv_expectation_and_grad": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), dp, sz, dp, dp],
+                                         C.c_int),
+            "qsv_expectation_and_grad_batch": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), dp, sz, sz,
+                                                dp, dp], C.c_int),
+            "qsv_expectation_batch": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), dp, sz, sz, dp],
+                                      C.c_int),
+            "qsv_param_shift_grad_batch": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), dp, sz, sz,
+                                            dp, dp], C.c_int),
+            "qsv_profile_read": ([vp, i32, dp, C.POINTER(i64), dp], C.c_int),
+            "qsv_plan_debug": ([C.POINTER(qsv_circuit), i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                                C.POINTER(C.c_uint64), i32], C.c_int),
+        }
+        for name, (args, res) in sigs.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != QSV_OK:
+        msg = lib().qsv_last_error().decode()
+        raise QsvError(status, msg or lib().qsv_status_string(status).decode())
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None and a.size else None
+
+
+# ------------------------------------------------------------------------------------------
+# Marshalling of circuit / Pauli-sum descriptions
+# ------------------------------------------------------------------------------------------
+class Circuit:
+    """A circuit description (dict with n_qubits and gates) as qsv_gate records."""
+
+    def __init__(self, circ):
+        self.n_qubits = int(circ["n_qubits"])
+        gates = circ["gates"]
+        self._gates = (qsv_gate * max(1, len(gates)))()
+        mats = []
+        n_params = 0
+        for i, g in enumerate(gates):
+            rec = self._gates[i]
+            rec.kind = GATE_KIND[g["kind"]]
+            t = list(g["targets"]) + [-1]
+            rec.targets[0], rec.targets[1] = int(t[0]), int(t[1])
+            cm = 0
+            for c in g["ctrls"]:
+                cm |= 1 << int(c)
+            rec.ctrl_mask = cm
+            for a in range(3):
+                rec.param_index[a] = -1
+                rec.param_coeff[a] = 0.0
+                rec.angle_const[a] = 0.0
+            for a, (idx, coeff, const) in enumerate(g["params"]):
+                rec.param_index[a] = int(idx)
+                rec.param_coeff[a] = float(coeff)
+                rec.angle_const[a] = float(const)
+                n_params = max(n_params, int(idx) + 1)
+            rec.matrix_offset = -1
+            if g["kind"] in ("MAT1", "MAT2"):
+                m = np.ascontiguousarray(g["matrix"], dtype=np.complex128).reshape(-1)
+                rec.matrix_offset = sum(len(x) for x in mats)
+                mats.append(m)
+        self._mats = (np.ascontiguousarray(np.concatenate(mats)).view(np.float64) if mats
+                      else np.zeros(0, np.float64))
+        self.n_params = n_params
+        self.c = qsv_circuit(self.n_qubits, 0, self._gates, len(gates), _dp(self._mats), self._mats.size)
+
+    @property
+    def ptr(self):
+        return C.byref(self.c)
+
+
+class PauliSum:
+    """Pauli sum [(coeff, ((qubit, 'X'|'Y'|'Z'), ...)), ...] as coefficient / mask arrays."""
+
+    def __init__(self, terms):
+        coeffs, xs, zs = [], [], []
+        for c, factors in terms:
+            xm = zm = 0
+            for q, p in factors:
+                if p in ("X", "Y"):
+                    xm |= 1 << int(q)
+                if p in ("Z", "Y"):
+                    zm |= 1 << int(q)
+            coeffs.append(float(c))
+            xs.append(xm)
+            zs.append(zm)
+        self._c = np.ascontiguousarray(coeffs, dtype=np.float64)
+        self._x = np.ascontiguousarray(xs, dtype=np.uint64)
+        self._z = np.ascontiguousarray(zs, dtype=np.uint64)
+        self.h = qsv_pauli_sum(len(coeffs), _dp(self._c),
+                               self._x.ctypes.data_as(C.POINTER(C.c_uint64)) if len(xs) else None,
+                               self._z.ctypes.data_as(C.POINTER(C.c_uint64)) if len(zs) else None)
+
+    @property
+    def ptr(self):
+        return C.byref(self.h)
+
+
+def _circuit(c):
+    return c if isinstance(c, Circuit) else Circuit(c)
+
+
+def _pauli(h):
+    return h if isinstance(h, PauliSum) else PauliSum(h)
+
+
+def _params(p):
+    return np.ascontiguousarray(np.zeros(0) if p is None else p, dtype=np.float64)
+
+
+# ------------------------------------------------------------------------------------------
+# States and the hot-path calls (same names as the C ABI, without the qsv_ prefix object)
+# ------------------------------------------------------------------------------------------
+class State:
+    """A device state vector (qsv_state*)."""
+
+    def __init__(self, handle, n_qubits, dtype, keepalive=None):
+        self.handle = C.c_void_p(handle)
+        self.n_qubits = n_qubits
+        self.dtype = dtype
+        self._keepalive = keepalive
+
+    def __del__(self):
+        try:
+            if self.handle and _lib is not None:
+                _lib.qsv_state_destroy(self.handle)
+                self.handle = C.c_void_p(None)
+        except Exception:
+            pass
+
+    @property
+    def np_dtype(self):
+        return np.complex64 if self.dtype == QSV_C64 else np.complex128
+
+
+def _dt(dtype):
+    if dtype in (QSV_C64, "c64", "complex64", np.complex64):
+        return QSV_C64
+    if dtype in (QSV_C128, "c128", "complex128", np.complex128):
+        return QSV_C128
+    raise ValueError(f"unknown dtype {dtype!r}")
+
+
+def qsv_state_create(n_qubits, dtype="c128"):
+    h = C.c_void_p()
+    dt = _dt(dtype)
+    check(lib().qsv_state_create(int(n_qubits), dt, C.byref(h)))
+    return State(h.value, int(n_qubits), dt)
+
+
+def qsv_state_wrap(device_ptr, n_qubits, dtype, keepalive=None):
+    h = C.c_void_p()
+    dt = _dt(dtype)
+    check(lib().qsv_state_wrap(C.c_void_p(device_ptr), int(n_qubits), dt, C.byref(h)))
+    return State(h.value, int(n_qubits), dt, keepalive)
+
+
+def qsv_state_destroy(s):
+    if s.handle:
+        check(lib().qsv_state_destroy(s.handle))
+        s.handle = C.c_void_p(None)
+
+
+def qsv_state_set_stream(s, stream_ptr):
+    check(lib().qsv_state_set_stream(s.handle, C.c_void_p(stream_ptr)))
+
+
+def qsv_state_synchronize(s):
+    check(lib().qsv_state_synchronize(s.handle))
+
+
+def qsv_state_reset(s):
+    check(lib().qsv_state_reset(s.handle))
+
+
+def qsv_state_set(s, amps):
+    a = np.ascontiguousarray(amps, dtype=s.np_dtype)
+    check(lib().qsv_state_set(s.handle, a.ctypes.data_as(C.c_void_p), a.size))
+
+
+def qsv_state_get(s):
+    out = np.empty(1 << s.n_qubits, dtype=s.np_dtype)
+    check(lib().qsv_state_get(s.handle, out.ctypes.data_as(C.c_void_p), out.size))
+    return out
+
+
+def qsv_state_copy(dst, src):
+    check(lib().qsv_state_copy(dst.handle, src.handle))
+
+
+def qsv_state_set_option(s, option, value):
+    check(lib().qsv_state_set_option(s.handle, int(option), int(value)))
+
+
+def qsv_state_get_option(s, option):
+    v = C.c_int64()
+    check(lib().qsv_state_get_option(s.handle, int(option), C.byref(v)))
+    return v.value
+
+
+def qsv_apply_circuit(s, circuit, params=None):
+    c = _circuit(circuit)
+    p = _params(params)
+    check(lib().qsv_apply_circuit(s.handle, c.ptr, _dp(p), p.size))
+
+
+def qsv_expectation(s, hamiltonian):
+    h = _pauli(hamiltonian)
+    re, im = C.c_double(), C.c_double()
+    check(lib().qsv_expectation(s.handle, h.ptr, C.byref(re), C.byref(im)))
+    return complex(re.value, im.value)
+
+
+def qsv_apply_pauli_sum(dst, src, hamiltonian):
+    h = _pauli(hamiltonian)
+    check(lib().qsv_apply_pauli_sum(dst.handle, src.handle, h.ptr))
+
+
+def qsv_expectation_and_grad(s, circuit, hamiltonian, params):
+    c, h, p = _circuit(circuit), _pauli(hamiltonian), _params(params)
+    E = C.c_double()
+    g = np.zeros(p.size, dtype=np.float64)
+    check(lib().qsv_expectation_and_grad(s.handle, c.ptr, h.ptr, _dp(p), p.size, C.byref(E), _dp(g)))
+    return E.value, g
+
+
+def _batch_params(params):
+    p = np.ascontiguousarray(np.atleast_2d(params), dtype=np.float64)
+    return p, p.shape[0], p.shape[1]
+
+
+def qsv_expectation_and_grad_batch(s, circuit, hamiltonian, params):
+    c, h = _circuit(circuit), _pauli(hamiltonian)
+    p, B, P = _batch_params(params)
+    E = np.zeros(B)
+    g = np.zeros((B, P))
+    check(lib().qsv_expectation_and_grad_batch(s.handle, c.ptr, h.ptr, _dp(p), B, P, _dp(E), _dp(g)))
+    return E, g
+
+
+def qsv_expectation_batch(s, circuit, hamiltonian, params):
+    c, h = _circuit(circuit), _pauli(hamiltonian)
+    p, B, P = _batch_params(params)
+    E = np.zeros(B)
+    check(lib().qsv_expectation_batch(s.handle, c.ptr, h.ptr, _dp(p), B, P, _dp(E)))
+    return E
+
+
+def qsv_param_shift_grad_batch(s, circuit, hamiltonian, params):
+    c, h = _circuit(circuit), _pauli(hamiltonian)
+    p, B, P = _batch_params(params)
+    E = np.zeros(B)
+    g = np.zeros((B, P))
+    check(lib().qsv_param_shift_grad_batch(s.handle, c.ptr, h.ptr, _dp(p), B, P, _dp(E), _dp(g)))
+    return E, g
+
+
+def qsv_profile_read(s, kernel_class):
+    """(total_ms, launches, algorithmic_bytes) of one kernel class since the last read."""
+    ms, n, b = C.c_double(), C.c_int64(), C.c_double()
+    check(lib().qsv_profile_read(s.handle, int(kernel_class), C.byref(ms), C.byref(n), C.byref(b)))
+    return ms.value, n.value, b.value
+
+
+def qsv_plan_debug(circuit, tile_qubits):
+    c = _circuit(circuit)
+    n = int(c.c.n_gates)
+    order = (C.c_int32 * max(n, 1))()
+    pass_of = (C.c_int32 * max(n, 1))()
+    n_passes = C.c_int32()
+    masks = (C.c_uint64 * max(n, 1))()
+    check(lib().qsv_plan_debug(c.ptr, int(tile_qubits), order, pass_of, C.byref(n_passes), masks, max(n, 1)))
+    return (np.array(order[:n]), np.array(pass_of[:n]), int(n_passes.value),
+            np.array(masks[:n_passes.value], dtype=np.uint64))

@@ -1,0 +1,833 @@
+// C ABI of the engine: state management, uploads, pass orchestration, reductions.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/qsv.h"
+#include "engine.h"
+#include "qsv_kernels.h"
+
+using namespace qsv;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+[[noreturn]] void fail(int status, const std::string& msg) { throw Error{status, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(e == hipErrorOutOfMemory ? QSV_ENOMEM : QSV_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void reserve(size_t need) {
+    if (need <= bytes) return;
+    if (p) hip_check(hipFree(p), "hipFree");
+    p = nullptr;
+    bytes = 0;
+    hip_check(hipMalloc(&p, need), "hipMalloc workspace");
+    bytes = need;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct qsv_state {
+  int32_t n = 0;
+  int32_t dtype = 0;
+  int device = 0;
+  void* psi = nullptr;
+  bool owned = false;
+  hipStream_t stream = nullptr;
+  int64_t opt[QSV_OPT_COUNT] = {0, 0, 0, 0};
+  // profiling: per kernel class, pending (start, stop) event pairs and bytes
+  struct Rec { hipEvent_t a, b; int cls; double bytes; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> free_events;
+  double prof_ms[QSV_K_COUNT] = {0, 0, 0, 0, 0};
+  int64_t prof_n[QSV_K_COUNT] = {0, 0, 0, 0, 0};
+  double prof_bytes[QSV_K_COUNT] = {0, 0, 0, 0, 0};
+  DevBuf ws_psi, ws_lam, upload, partials, gpart, outbuf, pauli;
+  // pinned staging for uploads and downloads, guarded by an event
+  void* stage = nullptr;
+  size_t stage_bytes = 0;
+  hipEvent_t stage_ev = nullptr;
+  bool stage_pending = false;
+  std::unordered_map<std::string, std::unique_ptr<Plan>> plans;
+
+  size_t amp_bytes() const { return dtype == QSV_C64 ? 8 : 16; }
+  uint64_t namps() const { return 1ull << n; }
+};
+
+namespace {
+
+void set_device(qsv_state* s) { hip_check(hipSetDevice(s->device), "hipSetDevice"); }
+
+hipEvent_t take_event(qsv_state* s) {
+  if (!s->free_events.empty()) {
+    hipEvent_t e = s->free_events.back();
+    s->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  hip_check(hipEventCreate(&e), "hipEventCreate");
+  return e;
+}
+
+// Collect finished profiling records into the per-class totals.
+void prof_collect(qsv_state* s) {
+  for (auto& r : s->recs) {
+    hip_check(hipEventSynchronize(r.b), "hipEventSynchronize");
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+    s->prof_ms[r.cls] += ms;
+    s->prof_n[r.cls] += 1;
+    s->prof_bytes[r.cls] += r.bytes;
+    s->free_events.push_back(r.a);
+    s->free_events.push_back(r.b);
+  }
+  s->recs.clear();
+}
+
+// Time one launch (when profiling is on).
+template <typename F>
+void timed(qsv_state* s, int cls, double bytes, F&& launch, const char* what) {
+  if (!s->opt[QSV_OPT_PROFILE]) {
+    hip_check(launch(), what);
+    return;
+  }
+  if (s->recs.size() > 4096) prof_collect(s);
+  hipEvent_t a = take_event(s), b = take_event(s);
+  hip_check(hipEventRecord(a, s->stream), "hipEventRecord");
+  hip_check(launch(), what);
+  hip_check(hipEventRecord(b, s->stream), "hipEventRecord");
+  s->recs.push_back({a, b, cls, bytes});
+}
+
+void* stage_acquire(qsv_state* s, size_t bytes) {
+  if (s->stage_pending) {
+    hip_check(hipEventSynchronize(s->stage_ev), "hipEventSynchronize");
+    s->stage_pending = false;
+  }
+  if (bytes > s->stage_bytes) {
+    if (s->stage) (void)hipHostFree(s->stage);
+    s->stage = nullptr;
+    s->stage_bytes = 0;
+    const size_t nb = align_up(bytes, 1 << 20);
+    hip_check(hipHostMalloc(&s->stage, nb, hipHostMallocDefault), "hipHostMalloc staging");
+    s->stage_bytes = nb;
+  }
+  return s->stage;
+}
+
+void stage_release_after_queue(qsv_state* s) {
+  hip_check(hipEventRecord(s->stage_ev, s->stream), "hipEventRecord");
+  s->stage_pending = true;
+}
+
+// Default options per dtype.
+void default_options(qsv_state* s) {
+  s->opt[QSV_OPT_TILE_QUBITS] = s->dtype == QSV_C64 ? 13 : 12;
+  s->opt[QSV_OPT_ADJ_TILE_QUBITS] = s->dtype == QSV_C64 ? 12 : 11;
+  s->opt[QSV_OPT_THREADS] = 512;
+}
+
+PlanOptions plan_options(const qsv_state* s, bool adjoint, bool fuse_zz) {
+  PlanOptions o;
+  o.tile_qubits = (int32_t)(adjoint ? s->opt[QSV_OPT_ADJ_TILE_QUBITS] : s->opt[QSV_OPT_TILE_QUBITS]);
+  if (adjoint && o.tile_qubits == 0) o.tile_qubits = s->dtype == QSV_C64 ? 12 : 11;
+  o.low_qubits = s->dtype == QSV_C64 ? 4 : 3;
+  o.fuse_zz = fuse_zz;
+  o.dtype = s->dtype;
+  return o;
+}
+
+const Plan& get_plan(qsv_state* s, const qsv_circuit* c, bool adjoint, bool fuse_zz) {
+  const PlanOptions o = plan_options(s, adjoint, fuse_zz);
+  std::string key = structure_key(c, adjoint, o);
+  auto it = s->plans.find(key);
+  if (it != s->plans.end()) return *it->second;
+  if (s->plans.size() > 64) s->plans.clear();
+  auto p = std::make_unique<Plan>(build_plan(c, adjoint, o));
+  const Plan& ref = *p;
+  s->plans.emplace(std::move(key), std::move(p));
+  return ref;
+}
+
+// Device copies of a plan's op lists and of per-batch-item complex tables.
+struct Uploaded {
+  TileOp* ops = nullptr;
+  DiagEntry* diag = nullptr;
+  int32_t* edges = nullptr;
+  void* ctab = nullptr;
+  int64_t ctab_stride = 0;  // complex entries per batch item
+};
+
+// Pack one or two plans and their bound tables into one upload.
+struct UploadReq {
+  const Plan* plan;
+  const std::vector<cplx>* ctab;  // batch * plan->ctab_size entries
+  int batch;
+};
+
+void upload_plans(qsv_state* s, const UploadReq* reqs, int n_req, Uploaded* out) {
+  const size_t cs = s->amp_bytes();
+  size_t off = 0;
+  std::vector<size_t> o_ops(n_req), o_diag(n_req), o_edges(n_req), o_ctab(n_req);
+  for (int r = 0; r < n_req; ++r) {
+    const Plan& p = *reqs[r].plan;
+    o_ops[r] = off; off = align_up(off + p.ops.size() * sizeof(TileOp), 256);
+    o_diag[r] = off; off = align_up(off + p.diag.size() * sizeof(DiagEntry), 256);
+    o_edges[r] = off; off = align_up(off + p.edges.size() * sizeof(int32_t), 256);
+    o_ctab[r] = off; off = align_up(off + (size_t)reqs[r].batch * p.ctab_size * cs, 256);
+  }
+  const size_t total = off ? off : 256;
+  char* st = static_cast<char*>(stage_acquire(s, total));
+  for (int r = 0; r < n_req; ++r) {
+    const Plan& p = *reqs[r].plan;
+    if (!p.ops.empty()) std::memcpy(st + o_ops[r], p.ops.data(), p.ops.size() * sizeof(TileOp));
+    if (!p.diag.empty()) std::memcpy(st + o_diag[r], p.diag.data(), p.diag.size() * sizeof(DiagEntry));
+    if (!p.edges.empty()) std::memcpy(st + o_edges[r], p.edges.data(), p.edges.size() * sizeof(int32_t));
+    const std::vector<cplx>& ct = *reqs[r].ctab;
+    const size_t ne = (size_t)reqs[r].batch * p.ctab_size;
+    if (s->dtype == QSV_C64) {
+      float* d = reinterpret_cast<float*>(st + o_ctab[r]);
+      for (size_t k = 0; k < ne; ++k) { d[2 * k] = (float)ct[k].real(); d[2 * k + 1] = (float)ct[k].imag(); }
+    } else {
+      double* d = reinterpret_cast<double*>(st + o_ctab[r]);
+      for (size_t k = 0; k < ne; ++k) { d[2 * k] = ct[k].real(); d[2 * k + 1] = ct[k].imag(); }
+    }
+  }
+  s->upload.reserve(total);
+  hip_check(hipMemcpyAsync(s->upload.p, st, total, hipMemcpyHostToDevice, s->stream), "upload");
+  stage_release_after_queue(s);
+  char* d = static_cast<char*>(s->upload.p);
+  for (int r = 0; r < n_req; ++r) {
+    out[r].ops = reinterpret_cast<TileOp*>(d + o_ops[r]);
+    out[r].diag = reinterpret_cast<DiagEntry*>(d + o_diag[r]);
+    out[r].edges = reinterpret_cast<int32_t*>(d + o_edges[r]);
+    out[r].ctab = d + o_ctab[r];
+    out[r].ctab_stride = reqs[r].plan->ctab_size;
+  }
+}
+
+// Run a forward plan on batch states.  src (may equal psi) is read by the first pass with
+// stride src_bstride; all later work is in place on psi.
+void run_forward(qsv_state* s, const Plan& p, const Uploaded& u, void* psi, int64_t bstride, const void* src,
+                 int64_t src_bstride, int batch) {
+  const int n = s->n;
+  if (p.unfused) {
+    if (src != psi) {
+      hip_check(launch_broadcast_state(s->dtype, psi, bstride, batch, src, n, s->stream), "broadcast");
+      if (src_bstride != 0) fail(QSV_EINVAL, "internal: unfused forward with strided source");
+    }
+    for (size_t i = 0; i < p.prims.size(); ++i) {
+      const Prim& pr = p.prims[i];
+      // algorithmic bytes: every amplitude the gate changes is read and written once
+      const int nc = __builtin_popcountll(pr.cmask);
+      double frac = 1.0 / (double)(1ull << nc);
+      if (pr.type == P_SIGN) frac = 1.0 / (double)(1ull << (nc - 1));
+      const double bytes = 2.0 * frac * (double)batch * (double)s->namps() * (double)s->amp_bytes();
+      timed(s, QSV_K_GATE_STREAM, bytes, [&] {
+        if (pr.type == P_DENSE1)
+          return launch_gate1(s->dtype, psi, bstride, batch, n, pr.q0, pr.cmask, u.ctab, u.ctab_stride,
+                              p.stream_mat[i], s->stream);
+        if (pr.type == P_DENSE2)
+          return launch_gate2(s->dtype, psi, bstride, batch, n, pr.q0, pr.q1, pr.cmask, u.ctab, u.ctab_stride,
+                              p.stream_mat[i], s->stream);
+        return launch_diag(s->dtype, psi, bstride, batch, n, u.diag, p.stream_diag[i], 1, u.ctab, u.ctab_stride,
+                           s->stream);
+      }, "gate kernel launch");
+    }
+    return;
+  }
+  bool first = true;
+  for (const DevPass& dp : p.passes) {
+    PassArgs A{};
+    A.psi = psi;
+    A.lam = nullptr;
+    A.src = (first && src != psi) ? src : nullptr;
+    A.bstride = bstride;
+    A.src_bstride = src_bstride;
+    A.ops = u.ops + dp.op_first;
+    A.diag = u.diag;
+    A.edges = u.edges;
+    A.ctab = u.ctab;
+    A.ctab_bstride = u.ctab_stride;
+    A.partials = nullptr;
+    A.tile_mask = dp.tile_mask;
+    A.n_ops = dp.op_count;
+    A.n_qubits = n;
+    A.m = dp.m;
+    A.n_pslots = 0;
+    const double bytes = 2.0 * (double)batch * (double)s->namps() * (double)s->amp_bytes();
+    timed(s, QSV_K_TILE_FORWARD, bytes,
+          [&] { return launch_tile_pass(s->dtype, false, dp.maxm, A, 1ull << (n - dp.m), batch, s->stream); },
+          "tile pass");
+    first = false;
+  }
+  if (first && src != psi)  // empty circuit
+    hip_check(launch_broadcast_state(s->dtype, psi, bstride, batch, src, n, s->stream), "broadcast");
+}
+
+// Pauli-sum groups uploaded once per call.
+struct DevPauli {
+  std::vector<PauliGroup> groups;
+  std::vector<const uint64_t*> z;
+  std::vector<const double*> cre, cim;
+};
+
+DevPauli upload_pauli(qsv_state* s, const qsv_pauli_sum* h, DevBuf& buf) {
+  DevPauli dp;
+  dp.groups = group_pauli_sum(h);
+  size_t total = 0;
+  for (auto& g : dp.groups) total += align_up(g.zmasks.size() * 8, 256) * 3;
+  total = total ? total : 256;
+  char* st = static_cast<char*>(stage_acquire(s, total));
+  size_t off = 0;
+  std::vector<size_t> offs;
+  for (auto& g : dp.groups) {
+    const size_t sz = g.zmasks.size() * 8;
+    offs.push_back(off);
+    std::memcpy(st + off, g.zmasks.data(), sz);
+    off += align_up(sz, 256);
+    std::memcpy(st + off, g.cre.data(), sz);
+    off += align_up(sz, 256);
+    std::memcpy(st + off, g.cim.data(), sz);
+    off += align_up(sz, 256);
+  }
+  buf.reserve(total);
+  hip_check(hipMemcpyAsync(buf.p, st, total, hipMemcpyHostToDevice, s->stream), "upload pauli");
+  stage_release_after_queue(s);
+  char* d = static_cast<char*>(buf.p);
+  for (size_t i = 0; i < dp.groups.size(); ++i) {
+    const size_t sz = align_up(dp.groups[i].zmasks.size() * 8, 256);
+    dp.z.push_back(reinterpret_cast<const uint64_t*>(d + offs[i]));
+    dp.cre.push_back(reinterpret_cast<const double*>(d + offs[i] + sz));
+    dp.cim.push_back(reinterpret_cast<const double*>(d + offs[i] + 2 * sz));
+  }
+  return dp;
+}
+
+// Expectation partials (and optionally lambda = H psi) for batch states; returns the device
+// pointer of reduced columns [batch][2 * groups] in s->outbuf at byte offset out_off.
+void run_pauli(qsv_state* s, const DevPauli& dp, const void* psi, void* lam, int64_t bstride, int batch,
+               double* out_cols) {
+  const int G = (int)dp.groups.size();
+  const unsigned nblk = pauli_blocks(s->n);
+  const size_t need = (size_t)batch * 2 * G * nblk * sizeof(double);
+  s->partials.reserve(need ? need : 8);
+  if (lam && G == 0)
+    hip_check(launch_set_basis(s->dtype, lam, bstride, batch, s->n, ~0ull, s->stream), "zero lambda");
+  for (int g = 0; g < G; ++g) {
+    PauliGroupArgs A{};
+    A.psi = psi;
+    A.lam = lam;
+    A.bstride = bstride;
+    A.zmasks = dp.z[g];
+    A.cre = dp.cre[g];
+    A.cim = dp.cim[g];
+    A.partials = static_cast<double*>(s->partials.p);
+    A.xmask = dp.groups[g].xmask;
+    A.n_terms = (int32_t)dp.groups[g].zmasks.size();
+    A.n_qubits = s->n;
+    A.accumulate = g > 0 ? 1 : 0;
+    A.col = 2 * g;
+    A.ncols = 2 * G;
+    // read psi; write lambda (and read it when accumulating)
+    const double sb = (double)batch * (double)s->namps() * (double)s->amp_bytes();
+    const double bytes = sb * (1.0 + (lam ? 1.0 : 0.0) + (lam && g > 0 ? 1.0 : 0.0));
+    timed(s, QSV_K_PAULI, bytes, [&] { return launch_pauli_group(s->dtype, A, batch, s->stream); }, "pauli pass");
+  }
+  hip_check(launch_reduce_columns(static_cast<double*>(s->partials.p), nblk, (int64_t)batch * 2 * G, out_cols,
+                                  s->stream),
+            "reduce");
+}
+
+int guarded(const std::function<void()>& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return QSV_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return QSV_ENOMEM;
+  } catch (...) {
+    g_last_error = "unexpected internal error";
+    return QSV_EINVAL;
+  }
+}
+
+qsv_state* check_state(const qsv_state* s) {
+  if (!s) fail(QSV_EINVAL, "state is NULL");
+  return const_cast<qsv_state*>(s);
+}
+
+// Energies (and optionally gradients) of `batch` bound tables.  Shared by the batch entry
+// points and the parameter-shift comparator.
+void energies_and_grads(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h, const Plan& fwd,
+                        const std::vector<cplx>& ctab_fwd, const Plan* adj, const std::vector<cplx>* ctab_adj,
+                        int batch, double* out_E, std::vector<double>* gcols) {
+  const uint64_t N = s->namps();
+  const int64_t bstride = (int64_t)N;
+  s->ws_psi.reserve((size_t)batch * N * s->amp_bytes());
+  if (adj) s->ws_lam.reserve((size_t)batch * N * s->amp_bytes());
+  Uploaded up[2];
+  UploadReq req[2] = {{&fwd, &ctab_fwd, batch}, {adj, ctab_adj, batch}};
+  upload_plans(s, req, adj ? 2 : 1, up);
+  DevPauli dp = upload_pauli(s, h, s->pauli);
+  const int G = (int)dp.groups.size();
+  run_forward(s, fwd, up[0], s->ws_psi.p, bstride, s->psi, 0, batch);
+  // output columns: energies [batch][2G] then gradient slots [batch][P]
+  const int P = adj ? adj->n_pslots : 0;
+  const size_t ne = (size_t)batch * 2 * G, ng = (size_t)batch * P;
+  s->outbuf.reserve((ne + ng + 1) * sizeof(double));
+  double* d_out = static_cast<double*>(s->outbuf.p);
+  run_pauli(s, dp, s->ws_psi.p, adj ? s->ws_lam.p : nullptr, bstride, batch, d_out);
+  if (adj && P > 0) {
+    uint64_t max_tiles = 1;
+    for (const DevPass& ap : adj->passes) max_tiles = std::max<uint64_t>(max_tiles, 1ull << (s->n - ap.m));
+    s->gpart.reserve((size_t)batch * P * max_tiles * sizeof(double));
+    const uint64_t tiles = 1ull << (s->n - adj->passes[0].m);
+    for (const DevPass& ap : adj->passes) {
+      PassArgs A{};
+      A.psi = s->ws_psi.p;
+      A.lam = s->ws_lam.p;
+      A.src = nullptr;
+      A.bstride = bstride;
+      A.src_bstride = 0;
+      A.ops = up[1].ops + ap.op_first;
+      A.diag = up[1].diag;
+      A.edges = up[1].edges;
+      A.ctab = up[1].ctab;
+      A.ctab_bstride = up[1].ctab_stride;
+      A.partials = static_cast<double*>(s->gpart.p) + (size_t)ap.pslot_first * tiles;
+      A.tile_mask = ap.tile_mask;
+      A.n_ops = ap.op_count;
+      A.n_qubits = s->n;
+      A.m = ap.m;
+      A.n_pslots = P;
+      const double bytes = 4.0 * (double)batch * (double)s->namps() * (double)s->amp_bytes();
+      timed(s, QSV_K_TILE_ADJOINT, bytes,
+            [&] { return launch_tile_pass(s->dtype, true, ap.maxm, A, 1ull << (s->n - ap.m), batch, s->stream); },
+            "adjoint tile pass");
+    }
+    hip_check(launch_reduce_columns(static_cast<double*>(s->gpart.p), (int64_t)tiles, (int64_t)ng, d_out + ne,
+                                    s->stream),
+              "reduce gradients");
+  } else if (adj) {
+    // no gradient slots: still run the reverse sweep? nothing depends on it
+  }
+  double* host = static_cast<double*>(stage_acquire(s, (ne + ng + 1) * sizeof(double)));
+  hip_check(hipMemcpyAsync(host, d_out, (ne + ng) * sizeof(double), hipMemcpyDeviceToHost, s->stream), "download");
+  hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+  for (int b = 0; b < batch; ++b) {
+    double e = 0.0;
+    for (int g = 0; g < G; ++g) e += host[(size_t)b * 2 * G + 2 * g];
+    out_E[b] = e;
+  }
+  if (gcols) gcols->assign(host + ne, host + ne + ng);
+  (void)c;
+}
+
+}  // namespace
+
+// =============================================================================================
+extern "C" {
+
+const char* qsv_status_string(int status) {
+  switch (status) {
+    case QSV_OK: return "ok";
+    case QSV_EINVAL: return "invalid argument";
+    case QSV_ENOMEM: return "out of memory";
+    case QSV_EDTYPE: return "bad dtype";
+    case QSV_EHIP: return "HIP runtime error";
+    case QSV_ERANGE: return "size out of range";
+    case QSV_ENOTSUP: return "not supported";
+    default: return "unknown status";
+  }
+}
+
+const char* qsv_last_error(void) { return g_last_error.c_str(); }
+
+const char* qsv_version(void) { return "qsv 0.1 (gfx950)"; }
+
+static int state_init(qsv_state* s, int32_t n, int32_t dtype) {
+  s->n = n;
+  s->dtype = dtype;
+  default_options(s);
+  hip_check(hipGetDevice(&s->device), "hipGetDevice");
+  hip_check(hipEventCreateWithFlags(&s->stage_ev, hipEventDisableTiming), "hipEventCreate");
+  return 0;
+}
+
+int qsv_state_create(int32_t n_qubits, int32_t dtype, qsv_state** out) {
+  return guarded([&] {
+    if (!out) fail(QSV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (dtype != QSV_C64 && dtype != QSV_C128) fail(QSV_EDTYPE, "dtype must be QSV_C64 or QSV_C128");
+    if (n_qubits < 1 || n_qubits > 34) fail(QSV_ERANGE, "n_qubits must be in [1, 34]");
+    auto s = std::make_unique<qsv_state>();
+    state_init(s.get(), n_qubits, dtype);
+    const size_t bytes = s->namps() * s->amp_bytes();
+    hip_check(hipMalloc(&s->psi, bytes), "hipMalloc state");
+    s->owned = true;
+    hip_check(launch_set_basis(dtype, s->psi, 0, 1, n_qubits, 0, s->stream), "init state");
+    *out = s.release();
+  });
+}
+
+int qsv_state_wrap(void* device_ptr, int32_t n_qubits, int32_t dtype, qsv_state** out) {
+  return guarded([&] {
+    if (!out) fail(QSV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!device_ptr) fail(QSV_EINVAL, "device_ptr is NULL");
+    if (dtype != QSV_C64 && dtype != QSV_C128) fail(QSV_EDTYPE, "dtype must be QSV_C64 or QSV_C128");
+    if (n_qubits < 1 || n_qubits > 34) fail(QSV_ERANGE, "n_qubits must be in [1, 34]");
+    auto s = std::make_unique<qsv_state>();
+    state_init(s.get(), n_qubits, dtype);
+    s->psi = device_ptr;
+    s->owned = false;
+    *out = s.release();
+  });
+}
+
+int qsv_state_destroy(qsv_state* s) {
+  if (!s) return QSV_OK;
+  return guarded([&] {
+    (void)hipSetDevice(s->device);
+    (void)hipStreamSynchronize(s->stream);
+    if (s->owned && s->psi) (void)hipFree(s->psi);
+    s->ws_psi.release();
+    s->ws_lam.release();
+    s->upload.release();
+    s->partials.release();
+    s->gpart.release();
+    s->outbuf.release();
+    s->pauli.release();
+    if (s->stage) (void)hipHostFree(s->stage);
+    if (s->stage_ev) (void)hipEventDestroy(s->stage_ev);
+    for (auto& r : s->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (auto e : s->free_events) (void)hipEventDestroy(e);
+    delete s;
+  });
+}
+
+int qsv_state_set_stream(qsv_state* s, void* hip_stream) {
+  return guarded([&] {
+    check_state(s);
+    s->stream = static_cast<hipStream_t>(hip_stream);
+  });
+}
+
+int qsv_state_synchronize(qsv_state* s) {
+  return guarded([&] {
+    check_state(s);
+    set_device(s);
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+  });
+}
+
+int qsv_state_info(const qsv_state* s, int32_t* n_qubits, int32_t* dtype, void** device_ptr) {
+  return guarded([&] {
+    check_state(s);
+    if (n_qubits) *n_qubits = s->n;
+    if (dtype) *dtype = s->dtype;
+    if (device_ptr) *device_ptr = s->psi;
+  });
+}
+
+int qsv_state_reset(qsv_state* s) {
+  return guarded([&] {
+    check_state(s);
+    set_device(s);
+    timed(s, QSV_K_OTHER, (double)s->namps() * (double)s->amp_bytes(),
+          [&] { return launch_set_basis(s->dtype, s->psi, 0, 1, s->n, 0, s->stream); }, "reset");
+  });
+}
+
+int qsv_state_set(qsv_state* s, const void* host_amps, size_t n_amps) {
+  return guarded([&] {
+    check_state(s);
+    if (!host_amps) fail(QSV_EINVAL, "host_amps is NULL");
+    if (n_amps != s->namps()) fail(QSV_EINVAL, "n_amps must be 2^n_qubits");
+    set_device(s);
+    hip_check(hipMemcpyAsync(s->psi, host_amps, n_amps * s->amp_bytes(), hipMemcpyHostToDevice, s->stream),
+              "set state");
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+  });
+}
+
+int qsv_state_get(qsv_state* s, void* host_amps, size_t n_amps) {
+  return guarded([&] {
+    check_state(s);
+    if (!host_amps) fail(QSV_EINVAL, "host_amps is NULL");
+    if (n_amps != s->namps()) fail(QSV_EINVAL, "n_amps must be 2^n_qubits");
+    set_device(s);
+    hip_check(hipMemcpyAsync(host_amps, s->psi, n_amps * s->amp_bytes(), hipMemcpyDeviceToHost, s->stream),
+              "get state");
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+  });
+}
+
+int qsv_state_copy(qsv_state* dst, const qsv_state* src) {
+  return guarded([&] {
+    check_state(dst);
+    check_state(src);
+    if (dst->dtype != src->dtype) fail(QSV_EDTYPE, "dtype mismatch");
+    if (dst->n != src->n) fail(QSV_EINVAL, "n_qubits mismatch");
+    if (dst == src) return;
+    set_device(dst);
+    hip_check(hipMemcpyAsync(dst->psi, src->psi, dst->namps() * dst->amp_bytes(), hipMemcpyDeviceToDevice,
+                             dst->stream),
+              "copy state");
+  });
+}
+
+int qsv_state_set_option(qsv_state* s, int32_t option, int64_t value) {
+  return guarded([&] {
+    check_state(s);
+    if (option < 0 || option >= QSV_OPT_COUNT) fail(QSV_EINVAL, "unknown option");
+    if (option == QSV_OPT_TILE_QUBITS) {
+      if (value != 0 && (value < 2 || tile_capacity_host(s->dtype, false, (int)value) < 0))
+        fail(QSV_EINVAL, "tile width must be 0 or fit in LDS (c64 <= 14, c128 <= 13)");
+    } else if (option == QSV_OPT_ADJ_TILE_QUBITS) {
+      if (value < 2 || tile_capacity_host(s->dtype, true, (int)value) < 0)
+        fail(QSV_EINVAL, "adjoint tile width must fit psi and lambda in LDS (c64 <= 13, c128 <= 12)");
+    } else if (option == QSV_OPT_THREADS) {
+      if (value != 256 && value != 512 && value != 1024) fail(QSV_EINVAL, "threads must be 256, 512 or 1024");
+    } else if (option == QSV_OPT_PROFILE) {
+      if (value != 0 && value != 1) fail(QSV_EINVAL, "profile must be 0 or 1");
+    }
+    s->opt[option] = value;
+  });
+}
+
+int qsv_state_get_option(const qsv_state* s, int32_t option, int64_t* value) {
+  return guarded([&] {
+    check_state(s);
+    if (option < 0 || option >= QSV_OPT_COUNT || !value) fail(QSV_EINVAL, "bad option query");
+    *value = s->opt[option];
+  });
+}
+
+int qsv_apply_circuit(qsv_state* s, const qsv_circuit* c, const double* params, size_t n_params) {
+  return guarded([&] {
+    check_state(s);
+    validate_circuit(c, params ? n_params : 0, s->n);
+    set_device(s);
+    const Plan& p = get_plan(s, c, false, true);
+    std::vector<cplx> ctab(p.ctab_size);
+    bind_ctab(p, c, params, nullptr, 0, ctab.data());
+    Uploaded u;
+    UploadReq req{&p, &ctab, 1};
+    upload_plans(s, &req, 1, &u);
+    run_forward(s, p, u, s->psi, 0, s->psi, 0, 1);
+  });
+}
+
+int qsv_expectation(qsv_state* s, const qsv_pauli_sum* h, double* out_re, double* out_im) {
+  return guarded([&] {
+    check_state(s);
+    validate_pauli_sum(h, s->n);
+    set_device(s);
+    DevPauli dp = upload_pauli(s, h, s->pauli);
+    const int G = (int)dp.groups.size();
+    s->outbuf.reserve((2 * G + 1) * sizeof(double));
+    run_pauli(s, dp, s->psi, nullptr, 0, 1, static_cast<double*>(s->outbuf.p));
+    double* host = static_cast<double*>(stage_acquire(s, (2 * G + 1) * sizeof(double)));
+    if (G) hip_check(hipMemcpyAsync(host, s->outbuf.p, 2 * G * sizeof(double), hipMemcpyDeviceToHost, s->stream),
+                     "download");
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    double re = 0, im = 0;
+    for (int g = 0; g < G; ++g) { re += host[2 * g]; im += host[2 * g + 1]; }
+    if (out_re) *out_re = re;
+    if (out_im) *out_im = im;
+  });
+}
+
+int qsv_apply_pauli_sum(qsv_state* dst, const qsv_state* src, const qsv_pauli_sum* h) {
+  return guarded([&] {
+    check_state(dst);
+    check_state(src);
+    if (dst == src) fail(QSV_EINVAL, "dst must differ from src");
+    if (dst->dtype != src->dtype) fail(QSV_EDTYPE, "dtype mismatch");
+    if (dst->n != src->n) fail(QSV_EINVAL, "n_qubits mismatch");
+    validate_pauli_sum(h, dst->n);
+    set_device(dst);
+    DevPauli dp = upload_pauli(dst, h, dst->pauli);
+    const int G = (int)dp.groups.size();
+    dst->outbuf.reserve((2 * G + 1) * sizeof(double));
+    run_pauli(dst, dp, src->psi, dst->psi, 0, 1, static_cast<double*>(dst->outbuf.p));
+    hip_check(hipStreamSynchronize(dst->stream), "hipStreamSynchronize");
+  });
+}
+
+static void batch_common(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h, const double* params,
+                         size_t batch, size_t n_params, double* out_E) {
+  check_state(s);
+  if (batch < 1 || batch > 65535) fail(QSV_ERANGE, "batch must be in [1, 65535]");
+  if (!out_E) fail(QSV_EINVAL, "out_E is NULL");
+  if (n_params && !params) fail(QSV_EINVAL, "params is NULL");
+  validate_circuit(c, n_params, s->n);
+  validate_pauli_sum(h, s->n);
+  set_device(s);
+}
+
+int qsv_expectation_and_grad_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h,
+                                   const double* params, size_t batch, size_t n_params, double* out_E,
+                                   double* out_grad) {
+  return guarded([&] {
+    batch_common(s, c, h, params, batch, n_params, out_E);
+    if (n_params && !out_grad) fail(QSV_EINVAL, "out_grad is NULL");
+    const Plan& fwd = get_plan(s, c, false, true);
+    const Plan& adj = get_plan(s, c, true, true);
+    std::vector<cplx> cf((size_t)batch * fwd.ctab_size), ca((size_t)batch * adj.ctab_size);
+    for (size_t b = 0; b < batch; ++b) {
+      bind_ctab(fwd, c, params + b * n_params, nullptr, 0, cf.data() + b * fwd.ctab_size);
+      bind_ctab(adj, c, params + b * n_params, nullptr, 0, ca.data() + b * adj.ctab_size);
+    }
+    std::vector<double> gcols;
+    energies_and_grads(s, c, h, fwd, cf, &adj, &ca, (int)batch, out_E, &gcols);
+    const int P = adj.n_pslots;
+    for (size_t b = 0; b < batch; ++b) {
+      double* g = out_grad + b * n_params;
+      for (size_t k = 0; k < n_params; ++k) g[k] = 0.0;
+      for (int k = 0; k < P; ++k) g[adj.pslot_param[k]] += gcols[b * P + k];
+    }
+  });
+}
+
+int qsv_expectation_and_grad(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h, const double* params,
+                             size_t n_params, double* out_E, double* out_grad) {
+  return qsv_expectation_and_grad_batch(s, c, h, params, 1, n_params, out_E, out_grad);
+}
+
+int qsv_expectation_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h, const double* params,
+                          size_t batch, size_t n_params, double* out_E) {
+  return guarded([&] {
+    batch_common(s, c, h, params, batch, n_params, out_E);
+    const Plan& fwd = get_plan(s, c, false, true);
+    std::vector<cplx> cf((size_t)batch * fwd.ctab_size);
+    for (size_t b = 0; b < batch; ++b)
+      bind_ctab(fwd, c, params + b * n_params, nullptr, 0, cf.data() + b * fwd.ctab_size);
+    energies_and_grads(s, c, h, fwd, cf, nullptr, nullptr, (int)batch, out_E, nullptr);
+  });
+}
+
+int qsv_param_shift_grad_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h,
+                               const double* params, size_t batch, size_t n_params, double* out_E,
+                               double* out_grad) {
+  return guarded([&] {
+    batch_common(s, c, h, params, batch, n_params, out_E);
+    if (n_params && !out_grad) fail(QSV_EINVAL, "out_grad is NULL");
+    // every parameterized angle occurrence, shifted by +-pi/2
+    struct Occ { int gate, slot, param; double coeff; };
+    std::vector<Occ> occ;
+    for (size_t i = 0; i < c->n_gates; ++i) {
+      const qsv_gate& g = c->gates[i];
+      const int na = g.kind == QSV_GATE_U3 ? 3 : (g.kind >= QSV_GATE_RX && g.kind <= QSV_GATE_RZZ ? 1 : 0);
+      for (int a = 0; a < na; ++a) {
+        if (g.param_index[a] < 0) continue;
+        if (g.ctrl_mask) fail(QSV_ENOTSUP, "two-term parameter shift does not hold for controlled rotations");
+        occ.push_back({(int)i, a, g.param_index[a], g.param_coeff[a]});
+      }
+    }
+    const Plan& fwd = get_plan(s, c, false, false);
+    const size_t per = 1 + 2 * occ.size();  // unshifted + shifted variants
+    const size_t state_bytes = s->namps() * s->amp_bytes();
+    const size_t budget = std::max<size_t>((size_t)8 << 30, s->ws_psi.bytes);
+    size_t chunk = std::max<size_t>(1, std::min<size_t>(budget / state_bytes, 4096));
+    std::vector<double> energies(per);
+    for (size_t b = 0; b < batch; ++b) {
+      const double* pb = params + b * n_params;
+      std::vector<double> ang(3 * c->n_gates);
+      for (size_t i = 0; i < c->n_gates; ++i) gate_angles(c->gates[i], pb, &ang[3 * i]);
+      for (size_t v0 = 0; v0 < per; v0 += chunk) {
+        const size_t nv = std::min(chunk, per - v0);
+        std::vector<cplx> cf(nv * fwd.ctab_size);
+        for (size_t v = 0; v < nv; ++v) {
+          const size_t id = v0 + v;
+          AngleOverride ov{};
+          int nov = 0;
+          if (id > 0) {
+            const Occ& o = occ[(id - 1) / 2];
+            ov.gate = o.gate;
+            ov.slot = o.slot;
+            ov.angle = ang[3 * o.gate + o.slot] + (((id - 1) % 2 == 0) ? M_PI / 2 : -M_PI / 2);
+            nov = 1;
+          }
+          bind_ctab(fwd, c, pb, &ov, nov, cf.data() + v * fwd.ctab_size);
+        }
+        energies_and_grads(s, c, h, fwd, cf, nullptr, nullptr, (int)nv, energies.data() + v0, nullptr);
+      }
+      out_E[b] = energies[0];
+      double* g = out_grad + b * n_params;
+      for (size_t k = 0; k < n_params; ++k) g[k] = 0.0;
+      for (size_t k = 0; k < occ.size(); ++k)
+        g[occ[k].param] += occ[k].coeff * 0.5 * (energies[1 + 2 * k] - energies[2 + 2 * k]);
+    }
+  });
+}
+
+int qsv_profile_read(qsv_state* s, int32_t kernel_class, double* total_ms, int64_t* launches,
+                     double* algorithmic_bytes) {
+  return guarded([&] {
+    check_state(s);
+    if (kernel_class < 0 || kernel_class >= QSV_K_COUNT) fail(QSV_EINVAL, "unknown kernel class");
+    set_device(s);
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    prof_collect(s);
+    if (total_ms) *total_ms = s->prof_ms[kernel_class];
+    if (launches) *launches = s->prof_n[kernel_class];
+    if (algorithmic_bytes) *algorithmic_bytes = s->prof_bytes[kernel_class];
+    s->prof_ms[kernel_class] = 0;
+    s->prof_n[kernel_class] = 0;
+    s->prof_bytes[kernel_class] = 0;
+  });
+}
+
+int qsv_plan_debug(const qsv_circuit* c, int32_t tile_qubits, int32_t* order, int32_t* pass_of, int32_t* n_passes,
+                   uint64_t* tile_masks, int32_t max_passes) {
+  return guarded([&] {
+    validate_circuit(c, (size_t)1 << 30, -1);
+    if (!order || !pass_of || !n_passes) fail(QSV_EINVAL, "output arrays are NULL");
+    if (tile_qubits < 2 || tile_qubits > 34) fail(QSV_EINVAL, "tile_qubits must be in [2, 34]");
+    const std::vector<Prim> prims = lower_forward(c);
+    const std::vector<Pass> passes = plan_passes(prims, c->n_qubits, std::min(tile_qubits, c->n_qubits), 3);
+    size_t k = 0;
+    for (size_t p = 0; p < passes.size(); ++p) {
+      for (int32_t i : passes[p].prims) {
+        order[k] = prims[i].gate;
+        pass_of[k] = (int32_t)p;
+        ++k;
+      }
+      if (tile_masks && (int32_t)p < max_passes) tile_masks[p] = passes[p].tile_mask;
+    }
+    *n_passes = (int32_t)passes.size();
+  });
+}
+
+}  // extern "C"

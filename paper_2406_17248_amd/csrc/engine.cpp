@@ -1,0 +1,710 @@
+// Gate lowering, tile-pass planning and parameter binding (host, pure C++).
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <sstream>
+
+namespace qsv {
+
+namespace {
+
+const int kNAngles[QSV_GATE_KIND_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 3, 0, 0, 0};
+const int kNTargets[QSV_GATE_KIND_COUNT] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 1, 2, 1, 2};
+
+const cplx I1(0.0, 1.0);
+
+[[noreturn]] void fail(int status, const std::string& msg) { throw Error{status, msg}; }
+
+int popc(uint64_t v) { return __builtin_popcountll(v); }
+
+bool mat_is_diagonal(const qsv_circuit* c, const qsv_gate& g) {
+  const int d = g.kind == QSV_GATE_MAT1 ? 2 : 4;
+  const double* m = c->matrices + 2 * g.matrix_offset;
+  for (int r = 0; r < d; ++r)
+    for (int k = 0; k < d; ++k)
+      if (r != k && (m[2 * (r * d + k)] != 0.0 || m[2 * (r * d + k) + 1] != 0.0)) return false;
+  return true;
+}
+
+bool kind_is_diagonal(const qsv_circuit* c, const qsv_gate& g) {
+  switch (g.kind) {
+    case QSV_GATE_Z: case QSV_GATE_S: case QSV_GATE_SDG: case QSV_GATE_T: case QSV_GATE_TDG:
+    case QSV_GATE_RZ: case QSV_GATE_PS: case QSV_GATE_RZZ:
+      return true;
+    case QSV_GATE_MAT1: case QSV_GATE_MAT2:
+      return mat_is_diagonal(c, g);
+    default:
+      return false;
+  }
+}
+
+uint64_t target_mask(const qsv_gate& g) {
+  uint64_t m = 1ull << g.targets[0];
+  if (kNTargets[g.kind] == 2) m |= 1ull << g.targets[1];
+  return m;
+}
+
+void finish_masks(Prim& p) {
+  uint64_t t = 1ull << p.q0;
+  if (p.q1 >= 0) t |= 1ull << p.q1;
+  if (p.type == P_SIGN) {
+    p.nondiag = 0;
+    p.touched = p.cmask;
+  } else {
+    p.nondiag = (p.type == P_DENSE1 || p.type == P_DENSE2) ? t : 0;
+    p.touched = t | p.cmask;
+  }
+}
+
+Prim forward_prim(const qsv_circuit* c, int i) {
+  const qsv_gate& g = c->gates[i];
+  Prim p{};
+  p.gate = i;
+  p.q0 = g.targets[0];
+  p.q1 = kNTargets[g.kind] == 2 ? g.targets[1] : -1;
+  p.cmask = g.ctrl_mask;
+  p.recipe = M_GATE;
+  p.angle_slot = 0;
+  p.dagger = false;
+  p.gen = G_NONE;
+  p.param = -1;
+  p.coeff = 0.0;
+  if (g.kind == QSV_GATE_Z) {
+    p.type = P_SIGN;
+    p.recipe = M_SIGN;
+    p.cmask = g.ctrl_mask | (1ull << g.targets[0]);
+  } else if (kind_is_diagonal(c, g)) {
+    p.type = kNTargets[g.kind] == 2 ? P_DIAG2 : P_DIAG1;
+  } else {
+    p.type = kNTargets[g.kind] == 2 ? P_DENSE2 : P_DENSE1;
+  }
+  finish_masks(p);
+  return p;
+}
+
+int32_t gen_of_kind(int kind) {
+  switch (kind) {
+    case QSV_GATE_RX: return G_X;
+    case QSV_GATE_RY: return G_Y;
+    case QSV_GATE_RZ: return G_Z;
+    case QSV_GATE_PS: return G_PS;
+    case QSV_GATE_RXX: return G_XX;
+    case QSV_GATE_RYY: return G_YY;
+    case QSV_GATE_RZZ: return G_ZZ;
+    default: return G_NONE;
+  }
+}
+
+// ---- matrices ----------------------------------------------------------------------------
+// dense 2x2 / 4x4 row-major; diagonal kinds return the diagonal only.
+int gate_numbers(const qsv_circuit* c, const qsv_gate& g, const double* ang, cplx* out) {
+  const double h = 0.5 * ang[0];
+  switch (g.kind) {
+    case QSV_GATE_X: out[0] = 0; out[1] = 1; out[2] = 1; out[3] = 0; return 4;
+    case QSV_GATE_Y: out[0] = 0; out[1] = -I1; out[2] = I1; out[3] = 0; return 4;
+    case QSV_GATE_H: {
+      const double r = std::sqrt(0.5);
+      out[0] = r; out[1] = r; out[2] = r; out[3] = -r; return 4;
+    }
+    case QSV_GATE_S: out[0] = 1; out[1] = I1; return 2;
+    case QSV_GATE_SDG: out[0] = 1; out[1] = -I1; return 2;
+    case QSV_GATE_T: out[0] = 1; out[1] = std::polar(1.0, M_PI / 4); return 2;
+    case QSV_GATE_TDG: out[0] = 1; out[1] = std::polar(1.0, -M_PI / 4); return 2;
+    case QSV_GATE_RX: out[0] = std::cos(h); out[1] = -I1 * std::sin(h); out[2] = -I1 * std::sin(h); out[3] = std::cos(h); return 4;
+    case QSV_GATE_RY: out[0] = std::cos(h); out[1] = -std::sin(h); out[2] = std::sin(h); out[3] = std::cos(h); return 4;
+    case QSV_GATE_RZ: out[0] = std::polar(1.0, -h); out[1] = std::polar(1.0, h); return 2;
+    case QSV_GATE_PS: out[0] = 1; out[1] = std::polar(1.0, ang[0]); return 2;
+    case QSV_GATE_RXX: case QSV_GATE_RYY: {
+      for (int k = 0; k < 16; ++k) out[k] = 0;
+      for (int col = 0; col < 4; ++col) {
+        out[col * 4 + col] = std::cos(h);
+        // P(x)P maps |col> to s(col) |col ^ 3>
+        double s = 1.0;
+        if (g.kind == QSV_GATE_RYY) s = (popc(col) & 1) ? 1.0 : -1.0;
+        out[(col ^ 3) * 4 + col] = -I1 * std::sin(h) * s;
+      }
+      return 16;
+    }
+    case QSV_GATE_RZZ:
+      out[0] = std::polar(1.0, -h); out[1] = std::polar(1.0, h); out[2] = std::polar(1.0, h); out[3] = std::polar(1.0, -h);
+      return 4;
+    case QSV_GATE_U3: {
+      const double th = ang[0], ph = ang[1], la = ang[2];
+      out[0] = std::cos(th / 2);
+      out[1] = -std::polar(1.0, la) * std::sin(th / 2);
+      out[2] = std::polar(1.0, ph) * std::sin(th / 2);
+      out[3] = std::polar(1.0, ph + la) * std::cos(th / 2);
+      return 4;
+    }
+    case QSV_GATE_SWAP:
+      for (int k = 0; k < 16; ++k) out[k] = 0;
+      out[0] = 1; out[1 * 4 + 2] = 1; out[2 * 4 + 1] = 1; out[15] = 1;
+      return 16;
+    case QSV_GATE_MAT1: case QSV_GATE_MAT2: {
+      const int d = g.kind == QSV_GATE_MAT1 ? 2 : 4;
+      const double* m = c->matrices + 2 * g.matrix_offset;
+      const bool diag = mat_is_diagonal(c, g);
+      if (diag) {
+        for (int r = 0; r < d; ++r) out[r] = cplx(m[2 * (r * d + r)], m[2 * (r * d + r) + 1]);
+        return d;
+      }
+      for (int k = 0; k < d * d; ++k) out[k] = cplx(m[2 * k], m[2 * k + 1]);
+      return d * d;
+    }
+    default:
+      fail(QSV_EINVAL, "gate kind has no matrix");
+  }
+}
+
+void dagger_numbers(int type, cplx* v, int count) {
+  if (type == P_DENSE1 || type == P_DENSE2) {
+    const int d = type == P_DENSE1 ? 2 : 4;
+    cplx t[16];
+    for (int r = 0; r < d; ++r)
+      for (int k = 0; k < d; ++k) t[r * d + k] = std::conj(v[k * d + r]);
+    for (int k = 0; k < d * d; ++k) v[k] = t[k];
+  } else {
+    for (int k = 0; k < count; ++k) v[k] = std::conj(v[k]);
+  }
+}
+
+int prim_numbers(const Prim& p, const qsv_circuit* c, const double* ang, cplx* out) {
+  int cnt = 0;
+  const double a = ang[p.angle_slot];
+  switch (p.recipe) {
+    case M_GATE: cnt = gate_numbers(c, c->gates[p.gate], ang, out); break;
+    case M_RZ_ANGLE: out[0] = std::polar(1.0, -a / 2); out[1] = std::polar(1.0, a / 2); cnt = 2; break;
+    case M_RY_ANGLE:
+      out[0] = std::cos(a / 2); out[1] = -std::sin(a / 2); out[2] = std::sin(a / 2); out[3] = std::cos(a / 2);
+      cnt = 4;
+      break;
+    case M_CPHASE_HALF: out[0] = std::polar(1.0, a / 2); out[1] = out[0]; cnt = 2; break;
+    default: return 0;
+  }
+  if (p.dagger) dagger_numbers(p.type, out, cnt);
+  return cnt;
+}
+
+int prim_gen(const Prim& p, cplx* out) {
+  const double k = p.coeff;
+  switch (p.gen) {
+    case G_X: out[0] = 0; out[1] = k; out[2] = k; out[3] = 0; return 4;
+    case G_Y: out[0] = 0; out[1] = -I1 * k; out[2] = I1 * k; out[3] = 0; return 4;
+    case G_Z: out[0] = k; out[1] = -k; return 2;
+    case G_PS: out[0] = 0; out[1] = -2 * k; return 2;
+    case G_CPHASE: out[0] = -2 * k; out[1] = -2 * k; return 2;
+    case G_ZZ: out[0] = k; out[1] = -k; out[2] = -k; out[3] = k; return 4;
+    case G_XX: case G_YY:
+      for (int i = 0; i < 16; ++i) out[i] = 0;
+      for (int col = 0; col < 4; ++col) {
+        double s = 1.0;
+        if (p.gen == G_YY) s = (popc(col) & 1) ? 1.0 : -1.0;
+        out[(col ^ 3) * 4 + col] = k * s;
+      }
+      return 16;
+    default: return 0;
+  }
+}
+
+int prim_size(const Prim& p) {
+  switch (p.type) {
+    case P_DENSE1: return 4;
+    case P_DENSE2: return 16;
+    case P_DIAG1: return 2;
+    case P_DIAG2: return 4;
+    default: return 0;
+  }
+}
+
+}  // namespace
+
+// ---- validation -----------------------------------------------------------------------------
+void validate_circuit(const qsv_circuit* c, size_t n_params, int32_t n_state) {
+  if (!c) fail(QSV_EINVAL, "circuit is NULL");
+  const int n = c->n_qubits;
+  if (n < 1 || n > 34) fail(QSV_ERANGE, "n_qubits must be in [1, 34]");
+  if (n_state >= 0 && n != n_state) fail(QSV_EINVAL, "circuit n_qubits differs from the state's");
+  if (c->n_gates && !c->gates) fail(QSV_EINVAL, "gates is NULL");
+  const uint64_t full = (1ull << n) - 1;
+  for (size_t i = 0; i < c->n_gates; ++i) {
+    const qsv_gate& g = c->gates[i];
+    std::ostringstream where;
+    where << "gate " << i << ": ";
+    if (g.kind < 0 || g.kind >= QSV_GATE_KIND_COUNT) fail(QSV_EINVAL, where.str() + "unknown kind");
+    const int nt = kNTargets[g.kind];
+    for (int t = 0; t < nt; ++t)
+      if (g.targets[t] < 0 || g.targets[t] >= n) fail(QSV_EINVAL, where.str() + "target out of range");
+    if (nt == 2 && g.targets[0] == g.targets[1]) fail(QSV_EINVAL, where.str() + "duplicate targets");
+    if (g.ctrl_mask & ~full) fail(QSV_EINVAL, where.str() + "control out of range");
+    if (g.ctrl_mask & target_mask(g)) fail(QSV_EINVAL, where.str() + "control on a target");
+    for (int a = 0; a < 3; ++a) {
+      if (a < kNAngles[g.kind]) {
+        if (g.param_index[a] < -1 || (g.param_index[a] >= 0 && (size_t)g.param_index[a] >= n_params))
+          fail(QSV_EINVAL, where.str() + "param_index out of range");
+        if (!std::isfinite(g.angle_const[a]) || !std::isfinite(g.param_coeff[a]))
+          fail(QSV_EINVAL, where.str() + "non-finite angle");
+      } else if (g.param_index[a] != -1) {
+        fail(QSV_EINVAL, where.str() + "unused angle slot must have param_index -1");
+      }
+    }
+    if (g.kind == QSV_GATE_MAT1 || g.kind == QSV_GATE_MAT2) {
+      const int64_t need = g.kind == QSV_GATE_MAT1 ? 4 : 16;
+      if (!c->matrices || g.matrix_offset < 0 || (uint64_t)(2 * (g.matrix_offset + need)) > c->n_matrix_doubles)
+        fail(QSV_EINVAL, where.str() + "matrix out of range");
+      for (int k = 0; k < 2 * need; ++k)
+        if (!std::isfinite(c->matrices[2 * g.matrix_offset + k])) fail(QSV_EINVAL, where.str() + "non-finite matrix");
+    }
+  }
+}
+
+void validate_pauli_sum(const qsv_pauli_sum* h, int32_t n) {
+  if (!h) fail(QSV_EINVAL, "pauli sum is NULL");
+  if (h->n_terms && (!h->coeffs || !h->x_masks || !h->z_masks)) fail(QSV_EINVAL, "pauli sum arrays are NULL");
+  const uint64_t full = (1ull << n) - 1;
+  for (size_t k = 0; k < h->n_terms; ++k) {
+    if ((h->x_masks[k] | h->z_masks[k]) & ~full) fail(QSV_EINVAL, "pauli term acts on a qubit >= n");
+    if (!std::isfinite(h->coeffs[k])) fail(QSV_EINVAL, "non-finite pauli coefficient");
+  }
+}
+
+// ---- lowering -------------------------------------------------------------------------------
+std::vector<Prim> lower_forward(const qsv_circuit* c) {
+  std::vector<Prim> out;
+  out.reserve(c->n_gates);
+  for (size_t i = 0; i < c->n_gates; ++i) out.push_back(forward_prim(c, (int)i));
+  return out;
+}
+
+std::vector<Prim> lower_adjoint(const qsv_circuit* c) {
+  std::vector<Prim> out;
+  for (int i = (int)c->n_gates - 1; i >= 0; --i) {
+    const qsv_gate& g = c->gates[i];
+    const bool any_param = g.kind == QSV_GATE_U3 &&
+                           (g.param_index[0] >= 0 || g.param_index[1] >= 0 || g.param_index[2] >= 0);
+    if (any_param) {
+      // U3 = e^{i(phi+lam)/2} RZ(phi) RY(theta) RZ(lam); with controls the phase becomes
+      // exp(i (phi/2) Pi_c) exp(i (lam/2) Pi_c).  Forward order of the parts:
+      struct Part { int type, recipe, slot, gen; double scale; };
+      std::vector<Part> parts = {{P_DIAG1, M_RZ_ANGLE, 2, G_Z, 1.0},
+                                 {P_DENSE1, M_RY_ANGLE, 0, G_Y, 1.0},
+                                 {P_DIAG1, M_RZ_ANGLE, 1, G_Z, 1.0}};
+      if (g.ctrl_mask) {
+        parts.push_back({P_DIAG1, M_CPHASE_HALF, 1, G_CPHASE, 0.5});
+        parts.push_back({P_DIAG1, M_CPHASE_HALF, 2, G_CPHASE, 0.5});
+      }
+      for (int k = (int)parts.size() - 1; k >= 0; --k) {
+        Prim p{};
+        p.type = parts[k].type;
+        p.gate = i;
+        p.q0 = g.targets[0];
+        p.q1 = -1;
+        p.cmask = g.ctrl_mask;
+        p.recipe = parts[k].recipe;
+        p.angle_slot = parts[k].slot;
+        p.dagger = true;
+        const int pi = g.param_index[parts[k].slot];
+        p.param = pi;
+        p.gen = pi >= 0 ? parts[k].gen : G_NONE;
+        p.coeff = pi >= 0 ? parts[k].scale * g.param_coeff[parts[k].slot] : 0.0;
+        finish_masks(p);
+        out.push_back(p);
+      }
+      continue;
+    }
+    Prim p = forward_prim(c, i);
+    p.dagger = true;
+    if (kNAngles[g.kind] == 1 && g.param_index[0] >= 0) {
+      p.gen = gen_of_kind(g.kind);
+      p.param = g.param_index[0];
+      p.coeff = g.param_coeff[0];
+    }
+    out.push_back(p);
+  }
+  return out;
+}
+
+// ---- planning -------------------------------------------------------------------------------
+namespace {
+
+// Primitives of rem that can run in a pass over tile T (in order), given that a
+// primitive may move ahead of an unscheduled earlier one only when every qubit they share
+// is acted on diagonally by both.
+void schedule(const std::vector<Prim>& prims, const std::vector<int32_t>& rem, uint64_t T,
+              std::vector<int32_t>* sched, std::vector<int32_t>* left, int* n_dense) {
+  uint64_t blocked_any = 0, blocked_nd = 0;
+  int dense = 0;
+  for (int32_t i : rem) {
+    const Prim& p = prims[i];
+    const bool ok = (p.nondiag & ~T) == 0 && (p.nondiag & blocked_any) == 0 &&
+                    ((p.touched & ~p.nondiag) & blocked_nd) == 0;
+    if (ok) {
+      if (sched) sched->push_back(i);
+      if (p.nondiag) ++dense;
+    } else {
+      if (left) left->push_back(i);
+      blocked_any |= p.touched;
+      blocked_nd |= p.nondiag;
+    }
+  }
+  if (n_dense) *n_dense = dense;
+}
+
+}  // namespace
+
+std::vector<Pass> plan_passes(const std::vector<Prim>& prims, int32_t n, int32_t m, int32_t low_qubits) {
+  std::vector<Pass> passes;
+  std::vector<int32_t> rem(prims.size());
+  for (size_t i = 0; i < prims.size(); ++i) rem[i] = (int32_t)i;
+  const uint64_t full = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+  if (m >= n) {
+    Pass p;
+    p.tile_mask = full;
+    p.m = n;
+    p.prims = rem;
+    passes.push_back(p);
+    return passes;
+  }
+  // keep two free tile slots so any 2-qubit primitive can be scheduled
+  const int low = std::max(0, std::min(low_qubits, m - 2));
+  while (!rem.empty()) {
+    uint64_t T = (low > 0) ? ((1ull << low) - 1) : 0;
+    // earliest position at which each qubit is needed non-diagonally
+    std::vector<int> first_need(n, 1 << 30);
+    for (size_t k = 0; k < rem.size(); ++k) {
+      uint64_t nd = prims[rem[k]].nondiag;
+      while (nd) {
+        const int q = __builtin_ctzll(nd);
+        if (first_need[q] > (int)k) first_need[q] = (int)k;
+        nd &= nd - 1;
+      }
+    }
+    while (popc(T) < m) {
+      int best_q = -1, best_dense = -1, best_first = 1 << 30;
+      for (int q = 0; q < n; ++q) {
+        if (T >> q & 1) continue;
+        int dense = 0;
+        schedule(prims, rem, T | (1ull << q), nullptr, nullptr, &dense);
+        if (dense > best_dense || (dense == best_dense && first_need[q] < best_first)) {
+          best_q = q;
+          best_dense = dense;
+          best_first = first_need[q];
+        }
+      }
+      T |= 1ull << best_q;
+    }
+    Pass ps;
+    std::vector<int32_t> left;
+    schedule(prims, rem, T, &ps.prims, &left, nullptr);
+    if (ps.prims.empty()) {
+      // cannot happen with the tie-break above; keep a safe fallback
+      T = prims[rem[0]].nondiag;
+      for (int q = 0; popc(T) < m && q < n; ++q) T |= 1ull << q;
+      ps.prims.clear();
+      left.clear();
+      schedule(prims, rem, T, &ps.prims, &left, nullptr);
+    }
+    ps.tile_mask = T;
+    ps.m = popc(T);
+    passes.push_back(ps);
+    rem.swap(left);
+  }
+  return passes;
+}
+
+int tile_capacity_host(int dtype, bool adj, int m) {
+  static const int caps[] = {8, 10, 11, 12, 13, 14};
+  const size_t amp = dtype == 0 ? 8 : 16;
+  for (int c : caps) {
+    if (c < m) continue;
+    if (amp * ((size_t)1 << c) * (adj ? 2 : 1) > 131072) return -1;
+    return c;
+  }
+  return -1;
+}
+
+static bool same_binding(const qsv_gate& a, const qsv_gate& b) {
+  return a.param_index[0] == b.param_index[0] && a.param_coeff[0] == b.param_coeff[0] &&
+         a.angle_const[0] == b.angle_const[0];
+}
+
+static bool zz_fusable(const Prim& p, const qsv_circuit* c) {
+  return p.recipe == M_GATE && p.cmask == 0 && c->gates[p.gate].kind == QSV_GATE_RZZ;
+}
+
+Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
+  Plan plan;
+  plan.adjoint = adjoint;
+  plan.n_qubits = c->n_qubits;
+  plan.prims = adjoint ? lower_adjoint(c) : lower_forward(c);
+  const int n = c->n_qubits;
+  auto alloc = [&](int count) {
+    const int off = plan.ctab_size;
+    plan.ctab_size += count;
+    return off;
+  };
+  if (!adjoint && opt.tile_qubits == 0) {
+    plan.unfused = true;
+    for (size_t i = 0; i < plan.prims.size(); ++i) {
+      const Prim& p = plan.prims[i];
+      int mat = -1, de = -1;
+      const int sz = prim_size(p);
+      if (sz) {
+        mat = alloc(sz);
+        plan.fills.push_back({F_PRIM_MATRIX, (int32_t)i, 0, mat});
+      }
+      if (p.type == P_DIAG1 || p.type == P_DIAG2 || p.type == P_SIGN) {
+        DiagEntry d{};
+        d.kind = p.type == P_SIGN ? DIAG_SIGN : DIAG_PHASE;
+        d.q0 = p.q0;
+        d.q1 = p.type == P_DIAG2 ? p.q1 : -1;
+        d.mat = mat;
+        d.cmask = p.cmask;
+        d.gen = -1;
+        de = (int)plan.diag.size();
+        plan.diag.push_back(d);
+      }
+      plan.stream_mat.push_back(mat);
+      plan.stream_diag.push_back(de);
+    }
+    return plan;
+  }
+
+  const int m = std::min<int>(std::max(opt.tile_qubits, 2), n);
+  const int maxm = tile_capacity_host(opt.dtype, adjoint, m);
+  if (maxm < 0) fail(QSV_EINVAL, "tile width does not fit in LDS for this dtype");
+  const std::vector<Pass> passes = plan_passes(plan.prims, n, m, opt.low_qubits);
+  for (const Pass& ps : passes) {
+    DevPass dp{};
+    dp.tile_mask = ps.tile_mask;
+    dp.m = ps.m;
+    dp.maxm = maxm;
+    dp.op_first = (int32_t)plan.ops.size();
+    dp.pslot_first = plan.n_pslots;
+    int loc[64];
+    {
+      int r = 0;
+      for (int q = 0; q < 64; ++q) loc[q] = (ps.tile_mask >> q & 1) ? r++ : -1;
+    }
+    auto local_mask = [&](uint64_t gm) {
+      uint32_t lm = 0;
+      while (gm) {
+        const int q = __builtin_ctzll(gm);
+        lm |= 1u << loc[q];
+        gm &= gm - 1;
+      }
+      return lm;
+    };
+    std::vector<int32_t> op_param;  // gradient parameter of each op of this pass (-1 none)
+    const std::vector<int32_t>& seq = ps.prims;
+    size_t k = 0;
+    while (k < seq.size()) {
+      const Prim& p = plan.prims[seq[k]];
+      TileOp op{};
+      op.gen = -1;
+      op.pslot = -1;
+      op.flush = 0;
+      if (p.type == P_DENSE1 || p.type == P_DENSE2) {
+        op.type = p.type == P_DENSE1 ? OP_DENSE1 : OP_DENSE2;
+        op.a = loc[p.q0];
+        op.b = p.type == P_DENSE2 ? loc[p.q1] : 0;
+        op.lmask = local_mask(p.cmask & ps.tile_mask);
+        op.omask = p.cmask & ~ps.tile_mask;
+        op.mat = alloc(prim_size(p));
+        plan.fills.push_back({F_PRIM_MATRIX, seq[k], 0, op.mat});
+        if (adjoint && p.gen != G_NONE) {
+          op.gen = alloc(prim_size(p));
+          plan.fills.push_back({F_PRIM_GEN, seq[k], 0, op.gen});
+        }
+        plan.ops.push_back(op);
+        op_param.push_back(adjoint && p.gen != G_NONE ? p.param : -1);
+        ++k;
+        continue;
+      }
+      // diagonal primitives: a fused ZZ run, or a run of diagonal entries
+      if (opt.fuse_zz && zz_fusable(p, c)) {
+        size_t e = k + 1;
+        while (e < seq.size() && zz_fusable(plan.prims[seq[e]], c) &&
+               same_binding(c->gates[plan.prims[seq[e]].gate], c->gates[p.gate]) &&
+               plan.prims[seq[e]].param == p.param && plan.prims[seq[e]].coeff == p.coeff)
+          ++e;
+        if (e - k >= 2) {
+          op.type = OP_ZZ;
+          op.first = (int32_t)(plan.edges.size() / 2);
+          op.count = (int32_t)(e - k);
+          for (size_t r = k; r < e; ++r) {
+            plan.edges.push_back(plan.prims[seq[r]].q0);
+            plan.edges.push_back(plan.prims[seq[r]].q1);
+          }
+          op.mat = alloc(op.count + 1);
+          plan.fills.push_back({F_ZZ_PHASES, seq[k], op.count, op.mat});
+          if (adjoint && p.gen != G_NONE) {
+            op.gen = alloc(op.count + 1);
+            plan.fills.push_back({F_ZZ_GEN, seq[k], op.count, op.gen});
+          }
+          plan.ops.push_back(op);
+          op_param.push_back(adjoint && p.gen != G_NONE ? p.param : -1);
+          k = e;
+          continue;
+        }
+      }
+      op.type = OP_DIAG;
+      op.first = (int32_t)plan.diag.size();
+      int32_t run_param = -1;
+      size_t e = k;
+      while (e < seq.size()) {
+        const Prim& q = plan.prims[seq[e]];
+        if (!(q.type == P_DIAG1 || q.type == P_DIAG2 || q.type == P_SIGN)) break;
+        if (e > k && opt.fuse_zz && zz_fusable(q, c) && e + 1 < seq.size() &&
+            zz_fusable(plan.prims[seq[e + 1]], c) &&
+            same_binding(c->gates[plan.prims[seq[e + 1]].gate], c->gates[q.gate]))
+          break;  // let the ZZ run start its own op
+        const int32_t qp = (adjoint && q.gen != G_NONE) ? q.param : -1;
+        if (qp >= 0) {
+          if (run_param >= 0 && qp != run_param) break;
+          run_param = qp;
+        }
+        DiagEntry d{};
+        d.kind = q.type == P_SIGN ? DIAG_SIGN : DIAG_PHASE;
+        d.q0 = q.q0;
+        d.q1 = q.type == P_DIAG2 ? q.q1 : -1;
+        d.cmask = q.cmask;
+        d.mat = -1;
+        d.gen = -1;
+        if (q.type != P_SIGN) {
+          d.mat = alloc(prim_size(q));
+          plan.fills.push_back({F_PRIM_MATRIX, seq[e], 0, d.mat});
+        }
+        if (qp >= 0) {
+          d.gen = alloc(prim_size(q));
+          plan.fills.push_back({F_PRIM_GEN, seq[e], 0, d.gen});
+        }
+        plan.diag.push_back(d);
+        ++e;
+      }
+      op.count = (int32_t)(plan.diag.size() - op.first);
+      plan.ops.push_back(op);
+      op_param.push_back(run_param);
+      k = e;
+    }
+    // gradient slots: consecutive ops of one parameter share an accumulator
+    if (adjoint) {
+      int32_t cur = -1, last_op = -1, local = -1;
+      for (size_t i = 0; i < op_param.size(); ++i) {
+        const int32_t prm = op_param[i];
+        if (prm < 0) continue;
+        TileOp& o = plan.ops[dp.op_first + i];
+        if (prm != cur) {
+          if (last_op >= 0) plan.ops[last_op].flush = 1;
+          cur = prm;
+          ++local;
+          plan.pslot_param.push_back(prm);
+        }
+        o.pslot = local;
+        last_op = dp.op_first + (int32_t)i;
+      }
+      if (last_op >= 0) plan.ops[last_op].flush = 1;
+      dp.pslot_count = local + 1;
+      plan.n_pslots += dp.pslot_count;
+    }
+    dp.op_count = (int32_t)plan.ops.size() - dp.op_first;
+    plan.passes.push_back(dp);
+  }
+  return plan;
+}
+
+std::string structure_key(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
+  std::string key;
+  auto put = [&](const void* p, size_t n) { key.append(reinterpret_cast<const char*>(p), n); };
+  const int32_t head[6] = {c->n_qubits, adjoint ? 1 : 0, opt.tile_qubits, opt.low_qubits, opt.fuse_zz ? 1 : 0,
+                           opt.dtype};
+  put(head, sizeof(head));
+  for (size_t i = 0; i < c->n_gates; ++i) {
+    const qsv_gate& g = c->gates[i];
+    int32_t rec[8] = {g.kind, g.targets[0], kNTargets[g.kind] == 2 ? g.targets[1] : -1, -1, -1, -1, 0, 0};
+    for (int a = 0; a < kNAngles[g.kind]; ++a) rec[3 + a] = g.param_index[a];
+    if (g.kind == QSV_GATE_MAT1 || g.kind == QSV_GATE_MAT2) rec[6] = mat_is_diagonal(c, g) ? 1 : 0;
+    if (g.kind == QSV_GATE_RZZ && i > 0 && c->gates[i - 1].kind == QSV_GATE_RZZ)
+      rec[7] = same_binding(g, c->gates[i - 1]) ? 1 : 0;
+    if (g.kind == QSV_GATE_RZZ || (kNAngles[g.kind] > 0 && g.param_index[0] >= 0)) {
+      // the chain-rule factor decides ZZ fusion in the reverse sweep
+      put(&g.param_coeff[0], sizeof(double));
+    }
+    put(rec, sizeof(rec));
+    put(&g.ctrl_mask, sizeof(g.ctrl_mask));
+  }
+  return key;
+}
+
+void gate_angles(const qsv_gate& g, const double* params, double out[3]) {
+  for (int a = 0; a < 3; ++a) {
+    out[a] = 0.0;
+    if (a >= kNAngles[g.kind]) continue;
+    out[a] = g.angle_const[a];
+    if (g.param_index[a] >= 0) out[a] += g.param_coeff[a] * params[g.param_index[a]];
+  }
+}
+
+void bind_ctab(const Plan& p, const qsv_circuit* c, const double* params, const AngleOverride* ov, int n_ov,
+               cplx* out) {
+  std::vector<double> ang(3 * c->n_gates);
+  for (size_t i = 0; i < c->n_gates; ++i) gate_angles(c->gates[i], params, &ang[3 * i]);
+  for (int k = 0; k < n_ov; ++k) ang[3 * ov[k].gate + ov[k].slot] = ov[k].angle;
+  for (const Fill& f : p.fills) {
+    cplx* dst = out + f.offset;
+    switch (f.kind) {
+      case F_PRIM_MATRIX: {
+        const Prim& pr = p.prims[f.prim];
+        prim_numbers(pr, c, &ang[3 * pr.gate], dst);
+        break;
+      }
+      case F_PRIM_GEN:
+        prim_gen(p.prims[f.prim], dst);
+        break;
+      case F_ZZ_PHASES: {
+        const Prim& pr = p.prims[f.prim];
+        const double th = ang[3 * pr.gate];
+        const double sgn = pr.dagger ? 1.0 : -1.0;
+        for (int cc = 0; cc <= f.count; ++cc) dst[cc] = std::polar(1.0, sgn * 0.5 * th * (f.count - 2 * cc));
+        break;
+      }
+      case F_ZZ_GEN: {
+        const Prim& pr = p.prims[f.prim];
+        for (int cc = 0; cc <= f.count; ++cc) dst[cc] = cplx(pr.coeff * (double)(f.count - 2 * cc), 0.0);
+        break;
+      }
+      default:
+        break;
+    }
+  }
+}
+
+std::vector<PauliGroup> group_pauli_sum(const qsv_pauli_sum* h) {
+  std::vector<PauliGroup> groups;
+  std::map<uint64_t, size_t> index;
+  for (size_t k = 0; k < h->n_terms; ++k) {
+    const uint64_t xm = h->x_masks[k], zm = h->z_masks[k];
+    auto it = index.find(xm);
+    size_t gi;
+    if (it == index.end()) {
+      gi = groups.size();
+      index[xm] = gi;
+      groups.push_back(PauliGroup{xm, {}, {}, {}});
+    } else {
+      gi = it->second;
+    }
+    // i^{popcount(x & z)}
+    const int r = popc(xm & zm) & 3;
+    const double c = h->coeffs[k];
+    const double re[4] = {c, 0.0, -c, 0.0};
+    const double im[4] = {0.0, c, 0.0, -c};
+    groups[gi].zmasks.push_back(zm);
+    groups[gi].cre.push_back(re[r]);
+    groups[gi].cim.push_back(im[r]);
+  }
+  return groups;
+}
+
+}  // namespace qsv

@@ -1,0 +1,151 @@
+// Host side of the engine: gate lowering, tile-pass planning and parameter binding.
+// Pure C++ (no HIP calls), so it runs and is tested on machines without a GPU.
+#pragma once
+#include <complex>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/qsv.h"
+#include "qsv_ops.h"
+
+namespace qsv {
+
+using cplx = std::complex<double>;
+
+// Thrown inside the library only; converted to a status code at the ABI boundary.
+struct Error {
+  int status;
+  std::string msg;
+};
+
+// Generator G of a rotation exp(-i theta G / 2) (times the control projector): the
+// adjoint-method gradient of an angle is Im<lambda|G|psi> at the point after the gate.
+enum GenKind : int32_t {
+  G_NONE = 0, G_X, G_Y, G_Z, G_XX, G_YY, G_ZZ,
+  G_PS,      // diag(0, -2): PhaseShift(theta) = exp(-i theta diag(0,-2) / 2)
+  G_CPHASE,  // -2 on the control subspace (target identity): exp(i beta Pi_c)
+};
+
+// How a primitive's numbers are formed at bind time.
+enum MatRecipe : int32_t {
+  M_GATE = 0,    // the gate's own matrix (all angles)
+  M_RZ_ANGLE,    // RZ(angle[angle_slot]) - parts of a lowered U3
+  M_RY_ANGLE,    // RY(angle[angle_slot])
+  M_CPHASE_HALF, // exp(i angle[angle_slot] / 2) on the control subspace
+  M_SIGN,        // no numbers (sign flip)
+};
+
+enum PrimType : int32_t { P_DENSE1 = 0, P_DENSE2, P_DIAG1, P_DIAG2, P_SIGN };
+
+struct Prim {
+  int32_t  type;
+  int32_t  gate;        // source gate index
+  int32_t  q0, q1;      // targets (q1 = -1 for one qubit)
+  uint64_t cmask;       // controls (P_SIGN: every bit that must be 1)
+  int32_t  recipe;
+  int32_t  angle_slot;
+  bool     dagger;
+  int32_t  gen;         // GenKind
+  int32_t  param;       // parameter index receiving the gradient (-1: none)
+  double   coeff;       // chain-rule factor d angle / d param
+  // planning masks
+  uint64_t nondiag;     // qubits acted on non-diagonally (must be tile qubits)
+  uint64_t touched;     // every qubit involved (targets and controls)
+};
+
+struct Pass {
+  uint64_t tile_mask = 0;
+  int32_t  m = 0;
+  std::vector<int32_t> prims;  // primitive indices in execution order
+};
+
+// Where a ctab entry block comes from at bind time.
+enum FillKind : int32_t {
+  F_PRIM_MATRIX = 0,  // the primitive's matrix: 4 (dense1), 16 (dense2), 2 or 4 (diag) entries
+  F_PRIM_GEN,         // coeff * generator of the primitive: same sizes (diag: real weights)
+  F_ZZ_PHASES,        // exp(-+ i theta/2 (E - 2c)), c = 0..E (sign by dagger)
+  F_ZZ_GEN,           // coeff * (E - 2c) as real weights
+};
+struct Fill {
+  int32_t kind;
+  int32_t prim;       // primitive (for ZZ runs: the first RZZ of the run)
+  int32_t count;      // ZZ: number of edges
+  int32_t offset;     // ctab offset (complex entries)
+};
+
+struct DevPass {
+  uint64_t tile_mask;
+  int32_t  m;
+  int32_t  maxm;       // LDS capacity instantiation
+  int32_t  op_first, op_count;
+  int32_t  pslot_first, pslot_count;
+};
+
+// A fully planned execution (forward or adjoint reverse sweep) of one circuit structure.
+struct Plan {
+  bool adjoint = false;
+  bool unfused = false;     // per-primitive streaming kernels
+  int32_t n_qubits = 0;
+  std::vector<Prim> prims;
+  std::vector<DevPass> passes;
+  std::vector<TileOp> ops;
+  std::vector<DiagEntry> diag;
+  std::vector<int32_t> edges;
+  std::vector<Fill> fills;
+  int32_t ctab_size = 0;            // complex entries per batch item
+  std::vector<int32_t> pslot_param; // adjoint: parameter of each gradient slot
+  int32_t n_pslots = 0;
+  // unfused: one streaming launch per primitive
+  std::vector<int32_t> stream_mat;  // ctab offset per primitive
+  std::vector<int32_t> stream_diag; // diag entry per primitive (diag types)
+};
+
+struct PlanOptions {
+  int32_t tile_qubits = 12;   // 0: unfused
+  int32_t low_qubits = 3;     // always in the tile (coalescing)
+  bool    fuse_zz = true;     // fuse runs of equally-bound RZZ into one phase-table op
+  int32_t dtype = 1;
+};
+
+// Validate a circuit against n_params (and the state's n).  Throws Error.
+void validate_circuit(const qsv_circuit* c, size_t n_params, int32_t n_state);
+void validate_pauli_sum(const qsv_pauli_sum* h, int32_t n);
+
+// Lower gates into primitives: forward order, or the adjoint reverse sweep (daggered,
+// with generators).
+std::vector<Prim> lower_forward(const qsv_circuit* c);
+std::vector<Prim> lower_adjoint(const qsv_circuit* c);
+
+// Group primitives into tile passes (greedy; each pass maximizes the dense primitives it
+// can execute given the order constraints).
+std::vector<Pass> plan_passes(const std::vector<Prim>& prims, int32_t n, int32_t m, int32_t low_qubits);
+
+// Smallest LDS tile instantiation (in qubits) holding 2^m amplitudes of each staged state
+// (one for forward passes, psi and lambda for the adjoint) within 128 KiB, or -1.
+int tile_capacity_host(int dtype, bool adj, int m);
+
+// Full plan (passes + device op lists + binding recipe).
+Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt);
+
+// Structure key for plan caching.
+std::string structure_key(const qsv_circuit* c, bool adjoint, const PlanOptions& opt);
+
+// Fill one batch item's complex table (fp64) for the given parameter values; angle
+// overrides (for parameter shift) replace the bound angle of (gate, slot).
+struct AngleOverride { int32_t gate; int32_t slot; double angle; };
+void bind_ctab(const Plan& p, const qsv_circuit* c, const double* params,
+               const AngleOverride* ov, int n_ov, cplx* out);
+
+// Bound angles of one gate.
+void gate_angles(const qsv_gate& g, const double* params, double out[3]);
+
+// Pauli sum grouped by x-mask.
+struct PauliGroup {
+  uint64_t xmask;
+  std::vector<uint64_t> zmasks;
+  std::vector<double> cre, cim;   // coeff * i^{popcount(xmask & zmask)}
+};
+std::vector<PauliGroup> group_pauli_sum(const qsv_pauli_sum* h);
+
+}  // namespace qsv

@@ -1,0 +1,26 @@
+// Host-side launchers of the HIP kernels (defined in qsv_kernels.hip).
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "qsv_ops.h"
+
+namespace qsv {
+
+hipError_t launch_tile_pass(int dtype, bool adj, int maxm, const PassArgs& A, uint64_t n_tiles,
+                            int batch, hipStream_t s);
+hipError_t launch_gate1(int dtype, void* psi, int64_t bstride, int batch, int n, int t, uint64_t cmask,
+                        const void* ctab, int64_t ctab_bstride, int mat, hipStream_t s);
+hipError_t launch_gate2(int dtype, void* psi, int64_t bstride, int batch, int n, int ta, int tb,
+                        uint64_t cmask, const void* ctab, int64_t ctab_bstride, int mat, hipStream_t s);
+hipError_t launch_diag(int dtype, void* psi, int64_t bstride, int batch, int n, const DiagEntry* diag,
+                       int first, int count, const void* ctab, int64_t ctab_bstride, hipStream_t s);
+unsigned pauli_blocks(int n);
+hipError_t launch_pauli_group(int dtype, const PauliGroupArgs& A, int batch, hipStream_t s);
+hipError_t launch_reduce_columns(const double* in, int64_t len, int64_t ncols, double* out, hipStream_t s);
+hipError_t launch_set_basis(int dtype, void* psi, int64_t bstride, int batch, int n, uint64_t index,
+                            hipStream_t s);
+hipError_t launch_broadcast_state(int dtype, void* dst, int64_t bstride, int batch, const void* src, int n,
+                                  hipStream_t s);
+
+}  // namespace qsv

@@ -1,0 +1,529 @@
+// HIP kernels of the state-vector engine, written for gfx950 (CDNA4, wave64).
+//
+//  tile_pass      one fused pass: a workgroup stages a 2^m-amplitude tile (the sub-cube
+//                 spanned by the pass's tile qubits, low qubits included so every global
+//                 access is a run of >= 128 contiguous bytes) into LDS, applies the pass's
+//                 op list there, and writes it back: one HBM read + write of the state for
+//                 a whole run of gates.  The adjoint variant stages psi and lambda together,
+//                 applies U^dag to both and accumulates Im<lambda|G|psi> per gradient slot
+//                 in fp64 (wave shuffles, then LDS across waves, then one partial per tile).
+//  gate1/gate2/diag_stream
+//                 unfused per-gate passes over HBM (baseline path and tile-width 0).
+//  pauli_group    one read pass per group of Pauli terms sharing an x-mask: expectation
+//                 partials and, optionally, lambda = H psi.
+//  reduce_columns fixed-order fp64 sums of per-block partials (bitwise repeatable).
+#include <hip/hip_runtime.h>
+
+#include "qsv_kernels.h"
+
+namespace qsv {
+
+template <typename R> struct CT;
+template <> struct CT<float>  { using T = float2; };
+template <> struct CT<double> { using T = double2; };
+
+__device__ __forceinline__ float  fmaT(float a, float b, float c)    { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  C r;
+  r.x = fmaT(a.x, b.x, -a.y * b.y);
+  r.y = fmaT(a.x, b.y, a.y * b.x);
+  return r;
+}
+// u0 * v0 + u1 * v1
+template <typename C> __device__ __forceinline__ C cdot2(C u0, C v0, C u1, C v1) {
+  C r;
+  r.x = fmaT(u0.x, v0.x, fmaT(-u0.y, v0.y, fmaT(u1.x, v1.x, -u1.y * v1.y)));
+  r.y = fmaT(u0.x, v0.y, fmaT(u0.y, v0.x, fmaT(u1.x, v1.y, u1.y * v1.x)));
+  return r;
+}
+// Im(conj(w) * g) in fp64
+template <typename C> __device__ __forceinline__ double im_conj_mul(C w, C g) {
+  return (double)w.x * (double)g.y - (double)w.y * (double)g.x;
+}
+
+// Deposit the low bits of v into the set positions of mask (ascending).
+__device__ __forceinline__ uint64_t pdep64(uint64_t v, uint64_t mask) {
+  uint64_t r = 0;
+  while (mask && v) {
+    const uint64_t low = mask & (~mask + 1);
+    if (v & 1) r |= low;
+    v >>= 1;
+    mask &= mask - 1;
+  }
+  return r;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------------------------------
+// Fused tile pass.
+// ------------------------------------------------------------------------------------------
+template <typename R, int NT, int MAXM, bool ADJ>
+__global__ __launch_bounds__(NT) void tile_pass(PassArgs A) {
+  using C = typename CT<R>::T;
+  constexpr int LGNT = (NT == 1024) ? 10 : (NT == 512) ? 9 : 8;
+  __shared__ C sp[1 << MAXM];
+  __shared__ C sl[ADJ ? (1 << MAXM) : 1];
+  __shared__ double red[NT / 64];
+
+  const int tid = threadIdx.x;
+  const int m = A.m;
+  const int nloc = 1 << m;
+  const int ra = (nloc + NT - 1) / NT;       // amplitude slots per thread
+  const bool active = tid < nloc;
+  const uint64_t tile = blockIdx.x;
+  const int b = blockIdx.y;
+  const uint64_t full = (A.n_qubits >= 64) ? ~0ull : ((1ull << A.n_qubits) - 1);
+  const uint64_t base = pdep64(tile, full & ~A.tile_mask);
+  const uint64_t s_tid = pdep64((uint64_t)tid, A.tile_mask);
+  uint64_t hmask = A.tile_mask;               // tile bits above the thread bits
+  for (int i = 0; i < LGNT; ++i) hmask &= hmask - 1;
+
+  C* psi = reinterpret_cast<C*>(A.psi) + (int64_t)b * A.bstride;
+  C* lam = ADJ ? reinterpret_cast<C*>(A.lam) + (int64_t)b * A.bstride : nullptr;
+  const C* src = A.src ? reinterpret_cast<const C*>(A.src) + (int64_t)b * A.src_bstride : psi;
+  const C* T = reinterpret_cast<const C*>(A.ctab) + (int64_t)b * A.ctab_bstride;
+
+  if (active) {
+    for (int k = 0; k < ra; ++k) {
+      const int j = tid + k * NT;
+      const uint64_t x = base | s_tid | pdep64((uint64_t)k, hmask);
+      sp[j] = src[x];
+      if (ADJ) sl[j] = lam[x];
+    }
+  }
+  __syncthreads();
+
+  double acc = 0.0;
+  for (int oi = 0; oi < A.n_ops; ++oi) {
+    const TileOp op = A.ops[oi];
+    const bool on = (base & op.omask) == op.omask;
+    if (on && op.type == OP_DENSE1) {
+      const C u00 = T[op.mat], u01 = T[op.mat + 1], u10 = T[op.mat + 2], u11 = T[op.mat + 3];
+      C g00, g01, g10, g11;
+      const bool grad = ADJ && op.gen >= 0;
+      if (grad) { g00 = T[op.gen]; g01 = T[op.gen + 1]; g10 = T[op.gen + 2]; g11 = T[op.gen + 3]; }
+      const int a = op.a;
+      const int amask = (1 << a) - 1;
+      const uint32_t lm = op.lmask;
+      for (int p = tid; p < (nloc >> 1); p += NT) {
+        const int j0 = ((p >> a) << (a + 1)) | (p & amask);
+        const int j1 = j0 | (1 << a);
+        if (((uint32_t)j0 & lm) != lm) continue;
+        const C v0 = sp[j0], v1 = sp[j1];
+        if (ADJ) {
+          const C w0 = sl[j0], w1 = sl[j1];
+          if (grad) acc += im_conj_mul(w0, cdot2(g00, v0, g01, v1)) + im_conj_mul(w1, cdot2(g10, v0, g11, v1));
+          sl[j0] = cdot2(u00, w0, u01, w1);
+          sl[j1] = cdot2(u10, w0, u11, w1);
+        }
+        sp[j0] = cdot2(u00, v0, u01, v1);
+        sp[j1] = cdot2(u10, v0, u11, v1);
+      }
+    } else if (on && op.type == OP_DENSE2) {
+      const int a = op.a, bb = op.b;
+      const int lo = a < bb ? a : bb, hi = a < bb ? bb : a;
+      const uint32_t lm = op.lmask;
+      const bool grad = ADJ && op.gen >= 0;
+      for (int p = tid; p < (nloc >> 2); p += NT) {
+        int t = ((p >> lo) << (lo + 1)) | (p & ((1 << lo) - 1));
+        t = ((t >> hi) << (hi + 1)) | (t & ((1 << hi) - 1));
+        if (((uint32_t)t & lm) != lm) continue;
+        const int idx[4] = {t, t | (1 << a), t | (1 << bb), t | (1 << a) | (1 << bb)};
+        C v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = sp[idx[r]];
+        C o[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          o[r] = cdot2(T[op.mat + 4 * r], v[0], T[op.mat + 4 * r + 1], v[1]),
+          o[r] = cdot2(C{1, 0}, o[r], T[op.mat + 4 * r + 2], v[2]),
+          o[r] = cdot2(C{1, 0}, o[r], T[op.mat + 4 * r + 3], v[3]);
+        if (ADJ) {
+          C w[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) w[r] = sl[idx[r]];
+          if (grad) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              C g = cdot2(T[op.gen + 4 * r], v[0], T[op.gen + 4 * r + 1], v[1]);
+              g = cdot2(C{1, 0}, g, T[op.gen + 4 * r + 2], v[2]);
+              g = cdot2(C{1, 0}, g, T[op.gen + 4 * r + 3], v[3]);
+              acc += im_conj_mul(w[r], g);
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            C q = cdot2(T[op.mat + 4 * r], w[0], T[op.mat + 4 * r + 1], w[1]);
+            q = cdot2(C{1, 0}, q, T[op.mat + 4 * r + 2], w[2]);
+            q = cdot2(C{1, 0}, q, T[op.mat + 4 * r + 3], w[3]);
+            sl[idx[r]] = q;
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sp[idx[r]] = o[r];
+      }
+    } else if (on && op.type == OP_DIAG) {
+      if (active) {
+        for (int k = 0; k < ra; ++k) {
+          const int j = tid + k * NT;
+          const uint64_t x = base | s_tid | pdep64((uint64_t)k, hmask);
+          C ph = C{1, 0};
+          int sign = 0;
+          double gw = 0.0;
+          for (int e = 0; e < op.count; ++e) {
+            const DiagEntry d = A.diag[op.first + e];
+            if (d.kind == DIAG_SIGN) {
+              sign ^= (int)((x & d.cmask) == d.cmask);
+            } else if ((x & d.cmask) == d.cmask) {
+              const int idx = (int)((x >> d.q0) & 1) | (d.q1 >= 0 ? (int)((x >> d.q1) & 1) << 1 : 0);
+              ph = cmul(ph, T[d.mat + idx]);
+              if (ADJ && d.gen >= 0) gw += (double)T[d.gen + idx].x;
+            }
+          }
+          if (sign) { ph.x = -ph.x; ph.y = -ph.y; }
+          const C v = sp[j];
+          sp[j] = cmul(v, ph);
+          if (ADJ) {
+            const C w = sl[j];
+            acc += gw * im_conj_mul(w, v);
+            sl[j] = cmul(w, ph);
+          }
+        }
+      }
+    } else if (on && op.type == OP_ZZ) {
+      if (active) {
+        const int32_t* ed = A.edges + 2 * op.first;
+        for (int k = 0; k < ra; ++k) {
+          const int j = tid + k * NT;
+          const uint64_t x = base | s_tid | pdep64((uint64_t)k, hmask);
+          int c = 0;
+          for (int e = 0; e < op.count; ++e) c += (int)(((x >> ed[2 * e]) ^ (x >> ed[2 * e + 1])) & 1);
+          const C ph = T[op.mat + c];
+          const C v = sp[j];
+          sp[j] = cmul(v, ph);
+          if (ADJ) {
+            const C w = sl[j];
+            if (op.gen >= 0) acc += (double)T[op.gen + c].x * im_conj_mul(w, v);
+            sl[j] = cmul(w, ph);
+          }
+        }
+      }
+    }
+    if (ADJ && op.flush) {
+      const double v = wave_sum(acc);
+      if ((tid & 63) == 0) red[tid >> 6] = v;
+      __syncthreads();
+      if (tid == 0) {
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += red[w];
+        A.partials[((int64_t)b * A.n_pslots + op.pslot) * (int64_t)gridDim.x + (int64_t)tile] = s;
+      }
+      acc = 0.0;
+    }
+    __syncthreads();
+  }
+
+  if (active) {
+    for (int k = 0; k < ra; ++k) {
+      const int j = tid + k * NT;
+      const uint64_t x = base | s_tid | pdep64((uint64_t)k, hmask);
+      psi[x] = sp[j];
+      if (ADJ) lam[x] = sl[j];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Unfused per-gate passes (grid-stride over amplitude pairs / quads / amplitudes).
+// ------------------------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void gate1_stream(void* psi_, int64_t bstride, int n, int t,
+                                                    uint64_t cmask, const void* ctab_,
+                                                    int64_t ctab_bstride, int mat) {
+  using C = typename CT<R>::T;
+  C* psi = reinterpret_cast<C*>(psi_) + (int64_t)blockIdx.y * bstride;
+  const C* T = reinterpret_cast<const C*>(ctab_) + (int64_t)blockIdx.y * ctab_bstride + mat;
+  const C u00 = T[0], u01 = T[1], u10 = T[2], u11 = T[3];
+  const uint64_t half = 1ull << (n - 1);
+  const uint64_t lowm = (1ull << t) - 1;
+  for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < half; p += (uint64_t)gridDim.x * 256) {
+    const uint64_t x0 = ((p >> t) << (t + 1)) | (p & lowm);
+    if ((x0 & cmask) != cmask) continue;
+    const uint64_t x1 = x0 | (1ull << t);
+    const C v0 = psi[x0], v1 = psi[x1];
+    psi[x0] = cdot2(u00, v0, u01, v1);
+    psi[x1] = cdot2(u10, v0, u11, v1);
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void gate2_stream(void* psi_, int64_t bstride, int n, int ta, int tb,
+                                                    uint64_t cmask, const void* ctab_,
+                                                    int64_t ctab_bstride, int mat) {
+  using C = typename CT<R>::T;
+  C* psi = reinterpret_cast<C*>(psi_) + (int64_t)blockIdx.y * bstride;
+  const C* U = reinterpret_cast<const C*>(ctab_) + (int64_t)blockIdx.y * ctab_bstride + mat;
+  const int lo = ta < tb ? ta : tb, hi = ta < tb ? tb : ta;
+  const uint64_t quarter = 1ull << (n - 2);
+  for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < quarter; p += (uint64_t)gridDim.x * 256) {
+    uint64_t x = ((p >> lo) << (lo + 1)) | (p & ((1ull << lo) - 1));
+    x = ((x >> hi) << (hi + 1)) | (x & ((1ull << hi) - 1));
+    if ((x & cmask) != cmask) continue;
+    const uint64_t idx[4] = {x, x | (1ull << ta), x | (1ull << tb), x | (1ull << ta) | (1ull << tb)};
+    C v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = psi[idx[r]];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      C o = cdot2(U[4 * r], v[0], U[4 * r + 1], v[1]);
+      o = cdot2(C{1, 0}, o, U[4 * r + 2], v[2]);
+      o = cdot2(C{1, 0}, o, U[4 * r + 3], v[3]);
+      psi[idx[r]] = o;
+    }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void diag_stream(void* psi_, int64_t bstride, int n,
+                                                   const DiagEntry* diag, int first, int count,
+                                                   const void* ctab_, int64_t ctab_bstride) {
+  using C = typename CT<R>::T;
+  C* psi = reinterpret_cast<C*>(psi_) + (int64_t)blockIdx.y * bstride;
+  const C* T = reinterpret_cast<const C*>(ctab_) + (int64_t)blockIdx.y * ctab_bstride;
+  const uint64_t N = 1ull << n;
+  for (uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x; x < N; x += (uint64_t)gridDim.x * 256) {
+    C ph = C{1, 0};
+    int sign = 0;
+    for (int e = 0; e < count; ++e) {
+      const DiagEntry d = diag[first + e];
+      if (d.kind == DIAG_SIGN) {
+        sign ^= (int)((x & d.cmask) == d.cmask);
+      } else if ((x & d.cmask) == d.cmask) {
+        const int idx = (int)((x >> d.q0) & 1) | (d.q1 >= 0 ? (int)((x >> d.q1) & 1) << 1 : 0);
+        ph = cmul(ph, T[d.mat + idx]);
+      }
+    }
+    if (sign) { ph.x = -ph.x; ph.y = -ph.y; }
+    psi[x] = cmul(psi[x], ph);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Pauli-sum group pass.
+// ------------------------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void group_factor(const PauliGroupArgs& A, uint64_t x, double& fr, double& fi) {
+  fr = 0.0;
+  fi = 0.0;
+  for (int k = 0; k < A.n_terms; ++k) {
+    const double s = (__popcll(x & A.zmasks[k]) & 1) ? -1.0 : 1.0;
+    fr = __builtin_fma(s, A.cre[k], fr);
+    fi = __builtin_fma(s, A.cim[k], fi);
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void pauli_group(PauliGroupArgs A) {
+  using C = typename CT<R>::T;
+  __shared__ double red[2][4];
+  const C* psi = reinterpret_cast<const C*>(A.psi) + (int64_t)blockIdx.y * A.bstride;
+  C* lam = A.lam ? reinterpret_cast<C*>(A.lam) + (int64_t)blockIdx.y * A.bstride : nullptr;
+  const uint64_t N = 1ull << A.n_qubits;
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  double er = 0.0, ei = 0.0;
+  if (A.xmask == 0) {
+    for (uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x; x < N; x += stride) {
+      double fr, fi;
+      group_factor<R>(A, x, fr, fi);
+      const C v = psi[x];
+      const double p = (double)v.x * v.x + (double)v.y * v.y;
+      er += p * fr;
+      ei += p * fi;
+      if (lam) {
+        C o;
+        o.x = (R)(fr * v.x - fi * v.y);
+        o.y = (R)(fr * v.y + fi * v.x);
+        if (A.accumulate) { const C l = lam[x]; o.x += l.x; o.y += l.y; }
+        lam[x] = o;
+      }
+    }
+  } else {
+    const int h = 63 - __clzll(A.xmask);
+    const uint64_t lowm = (1ull << h) - 1;
+    for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < (N >> 1); p += stride) {
+      const uint64_t x = ((p >> h) << (h + 1)) | (p & lowm);
+      const uint64_t y = x ^ A.xmask;
+      const C vx = psi[x], vy = psi[y];
+      double fxr, fxi, fyr, fyi;
+      group_factor<R>(A, x, fxr, fxi);
+      group_factor<R>(A, y, fyr, fyi);
+      // (H psi)[y] += f(x) psi[x];  (H psi)[x] += f(y) psi[y]
+      const double axr = fxr * vx.x - fxi * vx.y, axi = fxr * vx.y + fxi * vx.x;
+      const double ayr = fyr * vy.x - fyi * vy.y, ayi = fyr * vy.y + fyi * vy.x;
+      // E += conj(vy) * a_x + conj(vx) * a_y
+      er += (double)vy.x * axr + (double)vy.y * axi + (double)vx.x * ayr + (double)vx.y * ayi;
+      ei += (double)vy.x * axi - (double)vy.y * axr + (double)vx.x * ayi - (double)vx.y * ayr;
+      if (lam) {
+        C oy, ox;
+        oy.x = (R)axr; oy.y = (R)axi;
+        ox.x = (R)ayr; ox.y = (R)ayi;
+        if (A.accumulate) {
+          const C ly = lam[y], lx = lam[x];
+          oy.x += ly.x; oy.y += ly.y; ox.x += lx.x; ox.y += lx.y;
+        }
+        lam[y] = oy;
+        lam[x] = ox;
+      }
+    }
+  }
+  er = wave_sum(er);
+  ei = wave_sum(ei);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { red[0][w] = er; red[1][w] = ei; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int64_t o = ((int64_t)blockIdx.y * A.ncols + A.col) * gridDim.x + blockIdx.x;
+    A.partials[o] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    A.partials[o + gridDim.x] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
+// out[c] = sum_{i < len} in[c * len + i], fixed order.
+__global__ __launch_bounds__(256) void reduce_columns(const double* in, int64_t len, double* out) {
+  __shared__ double red[4];
+  const double* col = in + (int64_t)blockIdx.x * len;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < len; i += 256) s += col[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// psi_b = |index> for every batch item.
+template <typename R>
+__global__ __launch_bounds__(256) void set_basis(void* psi_, int64_t bstride, uint64_t N, uint64_t index) {
+  using C = typename CT<R>::T;
+  C* psi = reinterpret_cast<C*>(psi_) + (int64_t)blockIdx.y * bstride;
+  for (uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x; x < N; x += (uint64_t)gridDim.x * 256) {
+    C v;
+    v.x = (x == index) ? (R)1 : (R)0;
+    v.y = (R)0;
+    psi[x] = v;
+  }
+}
+
+// dst_b = src (broadcast one state into batch items).
+template <typename R>
+__global__ __launch_bounds__(256) void broadcast_state(void* dst_, int64_t bstride, const void* src_, uint64_t N) {
+  using C = typename CT<R>::T;
+  C* dst = reinterpret_cast<C*>(dst_) + (int64_t)blockIdx.y * bstride;
+  const C* src = reinterpret_cast<const C*>(src_);
+  for (uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x; x < N; x += (uint64_t)gridDim.x * 256) dst[x] = src[x];
+}
+
+// ------------------------------------------------------------------------------------------
+// Host launchers.
+// ------------------------------------------------------------------------------------------
+static inline unsigned stream_blocks(uint64_t work) {
+  const uint64_t b = (work + 255) / 256;
+  return (unsigned)(b < 4096 ? (b ? b : 1) : 4096);
+}
+
+template <typename R, int NT, int MAXM, bool ADJ>
+static hipError_t tile_launch_one(const PassArgs& A, dim3 grid, hipStream_t s) {
+  constexpr size_t bytes = (size_t)(2 * sizeof(R)) * ((size_t)1 << MAXM) * (ADJ ? 2 : 1);
+  if constexpr (bytes <= 131072) {
+    tile_pass<R, NT, MAXM, ADJ><<<grid, NT, 0, s>>>(A);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <typename R, bool ADJ>
+static hipError_t tile_dispatch(int maxm, const PassArgs& A, uint64_t n_tiles, int batch, hipStream_t s) {
+  const dim3 grid((unsigned)n_tiles, (unsigned)batch);
+  switch (maxm) {
+    case 8:  return tile_launch_one<R, 256, 8, ADJ>(A, grid, s);
+    case 10: return tile_launch_one<R, 512, 10, ADJ>(A, grid, s);
+    case 11: return tile_launch_one<R, 512, 11, ADJ>(A, grid, s);
+    case 12: return tile_launch_one<R, 512, 12, ADJ>(A, grid, s);
+    case 13: return tile_launch_one<R, 1024, 13, ADJ>(A, grid, s);
+    case 14: return tile_launch_one<R, 1024, 14, ADJ>(A, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_tile_pass(int dtype, bool adj, int maxm, const PassArgs& A, uint64_t n_tiles,
+                            int batch, hipStream_t s) {
+  if (dtype == 0) return adj ? tile_dispatch<float, true>(maxm, A, n_tiles, batch, s)
+                             : tile_dispatch<float, false>(maxm, A, n_tiles, batch, s);
+  return adj ? tile_dispatch<double, true>(maxm, A, n_tiles, batch, s)
+             : tile_dispatch<double, false>(maxm, A, n_tiles, batch, s);
+}
+
+hipError_t launch_gate1(int dtype, void* psi, int64_t bstride, int batch, int n, int t, uint64_t cmask,
+                        const void* ctab, int64_t ctab_bstride, int mat, hipStream_t s) {
+  const dim3 grid(stream_blocks(1ull << (n - 1)), (unsigned)batch);
+  if (dtype == 0) gate1_stream<float><<<grid, 256, 0, s>>>(psi, bstride, n, t, cmask, ctab, ctab_bstride, mat);
+  else gate1_stream<double><<<grid, 256, 0, s>>>(psi, bstride, n, t, cmask, ctab, ctab_bstride, mat);
+  return hipGetLastError();
+}
+
+hipError_t launch_gate2(int dtype, void* psi, int64_t bstride, int batch, int n, int ta, int tb,
+                        uint64_t cmask, const void* ctab, int64_t ctab_bstride, int mat, hipStream_t s) {
+  const dim3 grid(stream_blocks(1ull << (n - 2)), (unsigned)batch);
+  if (dtype == 0) gate2_stream<float><<<grid, 256, 0, s>>>(psi, bstride, n, ta, tb, cmask, ctab, ctab_bstride, mat);
+  else gate2_stream<double><<<grid, 256, 0, s>>>(psi, bstride, n, ta, tb, cmask, ctab, ctab_bstride, mat);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag(int dtype, void* psi, int64_t bstride, int batch, int n, const DiagEntry* diag,
+                       int first, int count, const void* ctab, int64_t ctab_bstride, hipStream_t s) {
+  const dim3 grid(stream_blocks(1ull << n), (unsigned)batch);
+  if (dtype == 0) diag_stream<float><<<grid, 256, 0, s>>>(psi, bstride, n, diag, first, count, ctab, ctab_bstride);
+  else diag_stream<double><<<grid, 256, 0, s>>>(psi, bstride, n, diag, first, count, ctab, ctab_bstride);
+  return hipGetLastError();
+}
+
+unsigned pauli_blocks(int n) {
+  const uint64_t work = 1ull << (n > 0 ? n - 1 : 0);
+  return stream_blocks(work) < 2048 ? stream_blocks(work) : 2048;
+}
+
+hipError_t launch_pauli_group(int dtype, const PauliGroupArgs& A, int batch, hipStream_t s) {
+  const dim3 grid(pauli_blocks(A.n_qubits), (unsigned)batch);
+  if (dtype == 0) pauli_group<float><<<grid, 256, 0, s>>>(A);
+  else pauli_group<double><<<grid, 256, 0, s>>>(A);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_columns(const double* in, int64_t len, int64_t ncols, double* out, hipStream_t s) {
+  if (ncols <= 0) return hipSuccess;
+  reduce_columns<<<(unsigned)ncols, 256, 0, s>>>(in, len, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_basis(int dtype, void* psi, int64_t bstride, int batch, int n, uint64_t index, hipStream_t s) {
+  const dim3 grid(stream_blocks(1ull << n), (unsigned)batch);
+  if (dtype == 0) set_basis<float><<<grid, 256, 0, s>>>(psi, bstride, 1ull << n, index);
+  else set_basis<double><<<grid, 256, 0, s>>>(psi, bstride, 1ull << n, index);
+  return hipGetLastError();
+}
+
+hipError_t launch_broadcast_state(int dtype, void* dst, int64_t bstride, int batch, const void* src, int n,
+                                  hipStream_t s) {
+  const dim3 grid(stream_blocks(1ull << n), (unsigned)batch);
+  if (dtype == 0) broadcast_state<float><<<grid, 256, 0, s>>>(dst, bstride, src, 1ull << n);
+  else broadcast_state<double><<<grid, 256, 0, s>>>(dst, bstride, src, 1ull << n);
+  return hipGetLastError();
+}
+
+}  // namespace qsv

@@ -1,0 +1,90 @@
+// Device-side encoding of a fused tile pass, shared by the host planner and the kernels.
+//
+// A tile pass covers the state in tiles of 2^m amplitudes.  The tile's qubits T (a
+// 64-bit mask, always containing the lowest qubits so loads stay coalesced) are its
+// "local" bits: tile-local index j has bit i <-> the i-th lowest qubit of T.  Every other
+// bit of a global index x is fixed per tile (the tile's "base").  A workgroup loads one
+// tile into LDS, runs the pass's op list on it, and writes it back.
+#pragma once
+#include <stdint.h>
+
+namespace qsv {
+
+enum OpType : int32_t {
+  OP_DENSE1 = 0,  // 2x2 complex matrix on local bit a
+  OP_DENSE2 = 1,  // 4x4 complex matrix on local bits a (row/col bit 0) and b (bit 1)
+  OP_DIAG = 2,    // run of diagonal gates: DiagEntry[first .. first+count)
+  OP_ZZ = 3,      // exp(-i theta/2 * sum_e Z_u Z_v) over EdgeTable[first .. first+count):
+                  // amplitude x is multiplied by ctab[mat + c(x)], c(x) = #edges with
+                  // x_u != x_v
+};
+
+// Matrices, phases and generator weights live in a per-batch-item table of complex
+// numbers (ctab); ops refer to it by offset.
+struct TileOp {
+  int32_t  type;
+  int32_t  a, b;       // local target bits (DENSE1 / DENSE2)
+  uint32_t lmask;      // controls on local bits, in j-space: apply where (j & lmask) == lmask
+  uint64_t omask;      // controls on bits outside the tile: apply iff (base & omask) == omask
+  int32_t  mat;        // ctab offset of the matrix (DENSE) or phase table (ZZ)
+  int32_t  first;      // DIAG / ZZ: first entry
+  int32_t  count;      // DIAG / ZZ: number of entries
+  int32_t  gen;        // adjoint: ctab offset of the scaled generator (DENSE: 4/16 entries,
+                       // ZZ: count+1 real weights in .x), -1 if no gradient here
+  int32_t  pslot;      // adjoint: output column of the accumulated gradient (or -1)
+  int32_t  flush;      // adjoint: reduce the accumulator into pslot after this op
+};
+
+// One diagonal gate inside an OP_DIAG run.  The gate's qubits q0, q1 (q1 = -1 for one
+// qubit) and control mask are global positions; the phase applied to amplitude x is
+// ctab[mat + ((x>>q1 & 1) << 1 | (x>>q0 & 1))] when all control bits of x are set.
+// kind SIGN: the phase is -1 when all bits of smask are set in x, 1 otherwise (Z, CZ,
+// multi-controlled Z), and no table is read.
+enum DiagKind : int32_t { DIAG_PHASE = 0, DIAG_SIGN = 1 };
+struct DiagEntry {
+  int32_t  kind;
+  int32_t  q0, q1;
+  int32_t  mat;
+  uint64_t cmask;      // PHASE: controls; SIGN: all bits that must be 1
+  int32_t  gen;        // adjoint: ctab offset of 4 real generator weights (.x), or -1
+  int32_t  pad;
+};
+
+struct PassArgs {
+  void*        psi;           // state(s), batch item b at psi + b * bstride amplitudes
+  void*        lam;           // adjoint: costate(s), same layout
+  const void*  src;           // first forward pass: read from src (+ b * src_bstride)
+  int64_t      bstride;
+  int64_t      src_bstride;
+  const TileOp*    ops;
+  const DiagEntry* diag;
+  const int32_t*   edges;     // (u, v) pairs of global qubits
+  const void*  ctab;          // per batch item: ctab + b * ctab_bstride complex entries
+  int64_t      ctab_bstride;
+  double*      partials;      // adjoint: [batch][n_pslots][n_tiles]
+  uint64_t     tile_mask;
+  int32_t      n_ops;
+  int32_t      n_qubits;
+  int32_t      m;             // tile qubits = popcount(tile_mask)
+  int32_t      n_pslots;
+};
+
+// Pauli-sum pass over one group of terms sharing an x-mask.
+struct PauliGroupArgs {
+  const void*  psi;
+  void*        lam;           // output H psi (or NULL for expectation only)
+  int64_t      bstride;
+  const uint64_t* zmasks;     // terms of the group
+  const double*   cre;        // coefficient * i^{popcount(x & z)} (real part)
+  const double*   cim;        // (imaginary part)
+  double*      partials;      // [batch][ncols][nblocks]; this group writes columns col, col+1
+  uint64_t     xmask;
+  int32_t      n_terms;
+  int32_t      n_qubits;
+  int32_t      accumulate;    // lam += (1) or lam = (0)
+  int32_t      col;           // first partial column (real part; imaginary part at col + 1)
+  int32_t      ncols;
+  int32_t      pad;
+};
+
+}  // namespace qsv
