@@ -63,6 +63,10 @@ def run_cpu_baseline(n, depth, seconds):
     return json.loads(out.stdout.strip().splitlines()[-1])
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def qaoa_leg(Q, dtype, ps_sets):
     """Adjoint batch gradient (64 sets) vs GPU parameter shift (ps_sets sets)."""
     import numpy as np
@@ -75,9 +79,11 @@ def qaoa_leg(Q, dtype, ps_sets):
     t0 = time.perf_counter()
     E, G = Q.qsv_expectation_and_grad_batch(s, c, h, params)
     t_adj = time.perf_counter() - t0
+    log(f"qaoa adjoint batch of {params.shape[0]}: {t_adj:.3f} s")
     t0 = time.perf_counter()
     Eps, Gps = Q.qsv_param_shift_grad_batch(s, c, h, params[:ps_sets])
     t_ps = time.perf_counter() - t0
+    log(f"qaoa parameter shift, {ps_sets} set(s): {t_ps:.3f} s")
     adj_rate = params.shape[0] / t_adj
     ps_rate = ps_sets / t_ps
     scale = sum(abs(cf) for cf, _ in H)
@@ -132,8 +138,10 @@ def main():
         Q.qsv_apply_circuit(s, c)
         return Q.qsv_expectation(s, h).real
 
+    log(f"brick n={n} depth={depth} dtype={args.dtype}: warmup")
     for _ in range(args.warmup):
         step()
+    log("warmup done; timing")
     Q.qsv_state_set_option(s, Q.OPT_PROFILE, 1)
     for k in range(5):
         Q.qsv_profile_read(s, k)
@@ -144,6 +152,7 @@ def main():
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     prof = {k: Q.qsv_profile_read(s, k) for k in range(5)}
+    log(f"timed {args.steps} steps: {dt * 1e3:.2f} ms/step")
     Q.qsv_state_set_option(s, Q.OPT_PROFILE, 0)
 
     total_bytes = sum(b for (_, _, b) in prof.values()) / args.steps
@@ -177,6 +186,7 @@ def main():
         except Exception as ex:  # report, do not hide, a failure of the secondary leg
             out["qaoa"] = {"error": repr(ex)}
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, single thread)")
         out["cpu_baseline"] = run_cpu_baseline(n, depth, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
