@@ -60,6 +60,20 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Read-only tables (op lists, diagonal entries, edges, bound matrices, Pauli terms) are
+// read through the constant address space: uniform addresses then become scalar loads
+// through the scalar cache instead of vector memory instructions.
+#define QSV_CONST __attribute__((address_space(4)))
+template <typename T> __device__ __forceinline__ T ld(const T* p) { return *(const QSV_CONST T*)p; }
+template <typename C> __device__ __forceinline__ C ldc(const C* p) {
+  using R = decltype(p->x);
+  const QSV_CONST R* q = (const QSV_CONST R*)p;
+  C r;
+  r.x = q[0];
+  r.y = q[1];
+  return r;
+}
+
 // ------------------------------------------------------------------------------------------
 // Fused tile pass.
 // ------------------------------------------------------------------------------------------
@@ -67,6 +81,9 @@ template <typename R, int NT, int MAXM, bool ADJ>
 __global__ __launch_bounds__(NT) void tile_pass(PassArgs A) {
   using C = typename CT<R>::T;
   constexpr int LGNT = (NT == 1024) ? 10 : (NT == 512) ? 9 : 8;
+  constexpr int RA = ((1 << MAXM) + NT - 1) / NT;        // amplitude slots per thread (max)
+  constexpr int PP = ((1 << MAXM) / 2 + NT - 1) / NT;    // pairs per thread per 1-qubit op (max)
+  constexpr int QP = ((1 << MAXM) / 4 + NT - 1) / NT;    // quads per thread per 2-qubit op (max)
   __shared__ C sp[1 << MAXM];
   __shared__ C sl[ADJ ? (1 << MAXM) : 1];
   __shared__ double red[NT / 64];
@@ -74,7 +91,7 @@ __global__ __launch_bounds__(NT) void tile_pass(PassArgs A) {
   const int tid = threadIdx.x;
   const int m = A.m;
   const int nloc = 1 << m;
-  const int ra = (nloc + NT - 1) / NT;       // amplitude slots per thread
+  const int half = nloc >> 1, quarter = nloc >> 2;
   const bool active = tid < nloc;
   const uint64_t tile = blockIdx.x;
   const int b = blockIdx.y;
@@ -83,6 +100,9 @@ __global__ __launch_bounds__(NT) void tile_pass(PassArgs A) {
   const uint64_t s_tid = pdep64((uint64_t)tid, A.tile_mask);
   uint64_t hmask = A.tile_mask;               // tile bits above the thread bits
   for (int i = 0; i < LGNT; ++i) hmask &= hmask - 1;
+  uint64_t xk[RA];                            // global index of each amplitude slot
+#pragma unroll
+  for (int k = 0; k < RA; ++k) xk[k] = base | s_tid | pdep64((uint64_t)k, hmask);
 
   C* psi = reinterpret_cast<C*>(A.psi) + (int64_t)b * A.bstride;
   C* lam = ADJ ? reinterpret_cast<C*>(A.lam) + (int64_t)b * A.bstride : nullptr;
@@ -90,47 +110,71 @@ __global__ __launch_bounds__(NT) void tile_pass(PassArgs A) {
   const C* T = reinterpret_cast<const C*>(A.ctab) + (int64_t)b * A.ctab_bstride;
 
   if (active) {
-    for (int k = 0; k < ra; ++k) {
+#pragma unroll
+    for (int k = 0; k < RA; ++k) {
       const int j = tid + k * NT;
-      const uint64_t x = base | s_tid | pdep64((uint64_t)k, hmask);
-      sp[j] = src[x];
-      if (ADJ) sl[j] = lam[x];
+      if (j < nloc) {
+        sp[j] = src[xk[k]];
+        if (ADJ) sl[j] = lam[xk[k]];
+      }
     }
   }
   __syncthreads();
 
   double acc = 0.0;
   for (int oi = 0; oi < A.n_ops; ++oi) {
-    const TileOp op = A.ops[oi];
-    const bool on = (base & op.omask) == op.omask;
-    if (on && op.type == OP_DENSE1) {
-      const C u00 = T[op.mat], u01 = T[op.mat + 1], u10 = T[op.mat + 2], u11 = T[op.mat + 3];
+    const TileOp* O = A.ops + oi;
+    const int type = ld(&O->type);
+    const uint64_t omask = ld(&O->omask);
+    const bool on = (base & omask) == omask;
+    if (on && type == OP_DENSE1) {
+      const int mat = ld(&O->mat), gen = ld(&O->gen);
+      const C u00 = ldc(T + mat), u01 = ldc(T + mat + 1), u10 = ldc(T + mat + 2), u11 = ldc(T + mat + 3);
       C g00, g01, g10, g11;
-      const bool grad = ADJ && op.gen >= 0;
-      if (grad) { g00 = T[op.gen]; g01 = T[op.gen + 1]; g10 = T[op.gen + 2]; g11 = T[op.gen + 3]; }
-      const int a = op.a;
+      const bool grad = ADJ && gen >= 0;
+      if (grad) { g00 = ldc(T + gen); g01 = ldc(T + gen + 1); g10 = ldc(T + gen + 2); g11 = ldc(T + gen + 3); }
+      const int a = ld(&O->a);
       const int amask = (1 << a) - 1;
-      const uint32_t lm = op.lmask;
-      for (int p = tid; p < (nloc >> 1); p += NT) {
-        const int j0 = ((p >> a) << (a + 1)) | (p & amask);
-        const int j1 = j0 | (1 << a);
-        if (((uint32_t)j0 & lm) != lm) continue;
-        const C v0 = sp[j0], v1 = sp[j1];
-        if (ADJ) {
-          const C w0 = sl[j0], w1 = sl[j1];
-          if (grad) acc += im_conj_mul(w0, cdot2(g00, v0, g01, v1)) + im_conj_mul(w1, cdot2(g10, v0, g11, v1));
-          sl[j0] = cdot2(u00, w0, u01, w1);
-          sl[j1] = cdot2(u10, w0, u11, w1);
+      const uint32_t lm = ld(&O->lmask);
+      int j0[PP];
+      bool ok[PP];
+      C v0[PP], v1[PP], w0[PP], w1[PP];
+#pragma unroll
+      for (int i = 0; i < PP; ++i) {
+        const int p = tid + i * NT;
+        j0[i] = ((p >> a) << (a + 1)) | (p & amask);
+        ok[i] = p < half && (((uint32_t)j0[i] & lm) == lm);
+        if (ok[i]) {
+          v0[i] = sp[j0[i]];
+          v1[i] = sp[j0[i] | (1 << a)];
+          if (ADJ) { w0[i] = sl[j0[i]]; w1[i] = sl[j0[i] | (1 << a)]; }
         }
-        sp[j0] = cdot2(u00, v0, u01, v1);
-        sp[j1] = cdot2(u10, v0, u11, v1);
       }
-    } else if (on && op.type == OP_DENSE2) {
-      const int a = op.a, bb = op.b;
+#pragma unroll
+      for (int i = 0; i < PP; ++i) {
+        if (!ok[i]) continue;
+        if (ADJ) {
+          if (grad)
+            acc += im_conj_mul(w0[i], cdot2(g00, v0[i], g01, v1[i])) + im_conj_mul(w1[i], cdot2(g10, v0[i], g11, v1[i]));
+          sl[j0[i]] = cdot2(u00, w0[i], u01, w1[i]);
+          sl[j0[i] | (1 << a)] = cdot2(u10, w0[i], u11, w1[i]);
+        }
+        sp[j0[i]] = cdot2(u00, v0[i], u01, v1[i]);
+        sp[j0[i] | (1 << a)] = cdot2(u10, v0[i], u11, v1[i]);
+      }
+    } else if (on && type == OP_DENSE2) {
+      const int a = ld(&O->a), bb = ld(&O->b);
+      const int mat = ld(&O->mat), gen = ld(&O->gen);
       const int lo = a < bb ? a : bb, hi = a < bb ? bb : a;
-      const uint32_t lm = op.lmask;
-      const bool grad = ADJ && op.gen >= 0;
-      for (int p = tid; p < (nloc >> 2); p += NT) {
+      const uint32_t lm = ld(&O->lmask);
+      const bool grad = ADJ && gen >= 0;
+      C U[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) U[r] = ldc(T + mat + r);
+#pragma unroll
+      for (int i = 0; i < QP; ++i) {
+        const int p = tid + i * NT;
+        if (p >= quarter) continue;
         int t = ((p >> lo) << (lo + 1)) | (p & ((1 << lo) - 1));
         t = ((t >> hi) << (hi + 1)) | (t & ((1 << hi) - 1));
         if (((uint32_t)t & lm) != lm) continue;
@@ -138,12 +182,6 @@ __global__ __launch_bounds__(NT) void tile_pass(PassArgs A) {
         C v[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[r] = sp[idx[r]];
-        C o[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          o[r] = cdot2(T[op.mat + 4 * r], v[0], T[op.mat + 4 * r + 1], v[1]),
-          o[r] = cdot2(C{1, 0}, o[r], T[op.mat + 4 * r + 2], v[2]),
-          o[r] = cdot2(C{1, 0}, o[r], T[op.mat + 4 * r + 3], v[3]);
         if (ADJ) {
           C w[4];
 #pragma unroll
@@ -151,78 +189,107 @@ __global__ __launch_bounds__(NT) void tile_pass(PassArgs A) {
           if (grad) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              C g = cdot2(T[op.gen + 4 * r], v[0], T[op.gen + 4 * r + 1], v[1]);
-              g = cdot2(C{1, 0}, g, T[op.gen + 4 * r + 2], v[2]);
-              g = cdot2(C{1, 0}, g, T[op.gen + 4 * r + 3], v[3]);
-              acc += im_conj_mul(w[r], g);
+              C gsum = cdot2(ldc(T + gen + 4 * r), v[0], ldc(T + gen + 4 * r + 1), v[1]);
+              gsum = cdot2(C{1, 0}, gsum, ldc(T + gen + 4 * r + 2), v[2]);
+              gsum = cdot2(C{1, 0}, gsum, ldc(T + gen + 4 * r + 3), v[3]);
+              acc += im_conj_mul(w[r], gsum);
             }
           }
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            C q = cdot2(T[op.mat + 4 * r], w[0], T[op.mat + 4 * r + 1], w[1]);
-            q = cdot2(C{1, 0}, q, T[op.mat + 4 * r + 2], w[2]);
-            q = cdot2(C{1, 0}, q, T[op.mat + 4 * r + 3], w[3]);
+            C q = cdot2(U[4 * r], w[0], U[4 * r + 1], w[1]);
+            q = cdot2(C{1, 0}, q, U[4 * r + 2], w[2]);
+            q = cdot2(C{1, 0}, q, U[4 * r + 3], w[3]);
             sl[idx[r]] = q;
           }
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sp[idx[r]] = o[r];
+        for (int r = 0; r < 4; ++r) {
+          C o = cdot2(U[4 * r], v[0], U[4 * r + 1], v[1]);
+          o = cdot2(C{1, 0}, o, U[4 * r + 2], v[2]);
+          o = cdot2(C{1, 0}, o, U[4 * r + 3], v[3]);
+          sp[idx[r]] = o;
+        }
       }
-    } else if (on && op.type == OP_DIAG) {
+    } else if (on && type == OP_DIAG) {
+      const int first = ld(&O->first), count = ld(&O->count);
       if (active) {
-        for (int k = 0; k < ra; ++k) {
+        C v[RA], w[RA];
+#pragma unroll
+        for (int k = 0; k < RA; ++k) {
           const int j = tid + k * NT;
-          const uint64_t x = base | s_tid | pdep64((uint64_t)k, hmask);
+          if (j < nloc) { v[k] = sp[j]; if (ADJ) w[k] = sl[j]; }
+        }
+#pragma unroll
+        for (int k = 0; k < RA; ++k) {
+          const int j = tid + k * NT;
+          if (j >= nloc) continue;
+          const uint64_t x = xk[k];
           C ph = C{1, 0};
           int sign = 0;
           double gw = 0.0;
-          for (int e = 0; e < op.count; ++e) {
-            const DiagEntry d = A.diag[op.first + e];
-            if (d.kind == DIAG_SIGN) {
-              sign ^= (int)((x & d.cmask) == d.cmask);
-            } else if ((x & d.cmask) == d.cmask) {
-              const int idx = (int)((x >> d.q0) & 1) | (d.q1 >= 0 ? (int)((x >> d.q1) & 1) << 1 : 0);
-              ph = cmul(ph, T[d.mat + idx]);
-              if (ADJ && d.gen >= 0) gw += (double)T[d.gen + idx].x;
+          for (int e = 0; e < count; ++e) {
+            const DiagEntry* d = A.diag + first + e;
+            const uint64_t cm = ld(&d->cmask);
+            if (ld(&d->kind) == DIAG_SIGN) {
+              sign ^= (int)((x & cm) == cm);
+            } else if ((x & cm) == cm) {
+              const int q1 = ld(&d->q1);
+              const int idx = (int)((x >> ld(&d->q0)) & 1) | (q1 >= 0 ? (int)((x >> q1) & 1) << 1 : 0);
+              ph = cmul(ph, ldc(T + ld(&d->mat) + idx));
+              if (ADJ) {
+                const int dg = ld(&d->gen);
+                if (dg >= 0) gw += (double)ldc(T + dg + idx).x;
+              }
             }
           }
           if (sign) { ph.x = -ph.x; ph.y = -ph.y; }
-          const C v = sp[j];
-          sp[j] = cmul(v, ph);
+          sp[j] = cmul(v[k], ph);
           if (ADJ) {
-            const C w = sl[j];
-            acc += gw * im_conj_mul(w, v);
-            sl[j] = cmul(w, ph);
+            acc += gw * im_conj_mul(w[k], v[k]);
+            sl[j] = cmul(w[k], ph);
           }
         }
       }
-    } else if (on && op.type == OP_ZZ) {
+    } else if (on && type == OP_ZZ) {
+      const int first = ld(&O->first), count = ld(&O->count), mat = ld(&O->mat), gen = ld(&O->gen);
       if (active) {
-        const int32_t* ed = A.edges + 2 * op.first;
-        for (int k = 0; k < ra; ++k) {
+        const int32_t* ed = A.edges + 2 * first;
+        C v[RA], w[RA];
+#pragma unroll
+        for (int k = 0; k < RA; ++k) {
           const int j = tid + k * NT;
-          const uint64_t x = base | s_tid | pdep64((uint64_t)k, hmask);
-          int c = 0;
-          for (int e = 0; e < op.count; ++e) c += (int)(((x >> ed[2 * e]) ^ (x >> ed[2 * e + 1])) & 1);
-          const C ph = T[op.mat + c];
-          const C v = sp[j];
-          sp[j] = cmul(v, ph);
+          if (j < nloc) { v[k] = sp[j]; if (ADJ) w[k] = sl[j]; }
+        }
+        int cnt[RA];
+#pragma unroll
+        for (int k = 0; k < RA; ++k) cnt[k] = 0;
+        for (int e = 0; e < count; ++e) {
+          const int u = ld(ed + 2 * e), vv = ld(ed + 2 * e + 1);
+#pragma unroll
+          for (int k = 0; k < RA; ++k) cnt[k] += (int)(((xk[k] >> u) ^ (xk[k] >> vv)) & 1);
+        }
+#pragma unroll
+        for (int k = 0; k < RA; ++k) {
+          const int j = tid + k * NT;
+          if (j >= nloc) continue;
+          const C ph = ldc(T + mat + cnt[k]);
+          sp[j] = cmul(v[k], ph);
           if (ADJ) {
-            const C w = sl[j];
-            if (op.gen >= 0) acc += (double)T[op.gen + c].x * im_conj_mul(w, v);
-            sl[j] = cmul(w, ph);
+            if (gen >= 0) acc += (double)ldc(T + gen + cnt[k]).x * im_conj_mul(w[k], v[k]);
+            sl[j] = cmul(w[k], ph);
           }
         }
       }
     }
-    if (ADJ && op.flush) {
+    if (ADJ && ld(&O->flush)) {
       const double v = wave_sum(acc);
       if ((tid & 63) == 0) red[tid >> 6] = v;
       __syncthreads();
       if (tid == 0) {
         double s = 0.0;
         for (int w = 0; w < NT / 64; ++w) s += red[w];
-        A.partials[((int64_t)b * A.n_pslots + op.pslot) * (int64_t)gridDim.x + (int64_t)tile] = s;
+        A.partials[((int64_t)b * A.n_pslots + ld(&O->pslot)) * (int64_t)gridDim.x + (int64_t)tile] = s;
       }
       acc = 0.0;
     }
@@ -230,11 +297,13 @@ __global__ __launch_bounds__(NT) void tile_pass(PassArgs A) {
   }
 
   if (active) {
-    for (int k = 0; k < ra; ++k) {
+#pragma unroll
+    for (int k = 0; k < RA; ++k) {
       const int j = tid + k * NT;
-      const uint64_t x = base | s_tid | pdep64((uint64_t)k, hmask);
-      psi[x] = sp[j];
-      if (ADJ) lam[x] = sl[j];
+      if (j < nloc) {
+        psi[xk[k]] = sp[j];
+        if (ADJ) lam[xk[k]] = sl[j];
+      }
     }
   }
 }
@@ -301,12 +370,14 @@ __global__ __launch_bounds__(256) void diag_stream(void* psi_, int64_t bstride, 
     C ph = C{1, 0};
     int sign = 0;
     for (int e = 0; e < count; ++e) {
-      const DiagEntry d = diag[first + e];
-      if (d.kind == DIAG_SIGN) {
-        sign ^= (int)((x & d.cmask) == d.cmask);
-      } else if ((x & d.cmask) == d.cmask) {
-        const int idx = (int)((x >> d.q0) & 1) | (d.q1 >= 0 ? (int)((x >> d.q1) & 1) << 1 : 0);
-        ph = cmul(ph, T[d.mat + idx]);
+      const DiagEntry* d = diag + first + e;
+      const uint64_t cm = ld(&d->cmask);
+      if (ld(&d->kind) == DIAG_SIGN) {
+        sign ^= (int)((x & cm) == cm);
+      } else if ((x & cm) == cm) {
+        const int q1 = ld(&d->q1);
+        const int idx = (int)((x >> ld(&d->q0)) & 1) | (q1 >= 0 ? (int)((x >> q1) & 1) << 1 : 0);
+        ph = cmul(ph, ldc(T + ld(&d->mat) + idx));
       }
     }
     if (sign) { ph.x = -ph.x; ph.y = -ph.y; }
@@ -322,9 +393,9 @@ __device__ __forceinline__ void group_factor(const PauliGroupArgs& A, uint64_t x
   fr = 0.0;
   fi = 0.0;
   for (int k = 0; k < A.n_terms; ++k) {
-    const double s = (__popcll(x & A.zmasks[k]) & 1) ? -1.0 : 1.0;
-    fr = __builtin_fma(s, A.cre[k], fr);
-    fi = __builtin_fma(s, A.cim[k], fi);
+    const double s = (__popcll(x & ld(A.zmasks + k)) & 1) ? -1.0 : 1.0;
+    fr = __builtin_fma(s, ld(A.cre + k), fr);
+    fi = __builtin_fma(s, ld(A.cim + k), fi);
   }
 }
 
