@@ -217,12 +217,16 @@ int qsv_profile_read(qsv_state* s, int32_t kernel_class, double* total_ms, int64
                      double* algorithmic_bytes);
 
 /* ---- host-only diagnostics (no device work; usable without a GPU) ------------------- */
-/* Plan the fused execution of a circuit with tile width tile_qubits.  On return
- * order[i] is the index of the i-th gate executed, pass_of[i] its tile pass, and
- * *n_passes the number of passes; the arrays must hold n_gates entries.  tile_masks,
+/* Plan the fused execution of a circuit with tile width tile_qubits.  The circuit is
+ * first lowered into primitives (one per gate, except RXX and RYY, which become two
+ * basis changes on each side of a diagonal RZZ: five primitives).  On return, for
+ * i < *n_entries, order[i] is the gate index of the i-th primitive executed and
+ * pass_of[i] its tile pass; *n_passes is the number of passes.  order and pass_of hold
+ * max_entries entries (5 * n_gates always suffices; QSV_ERANGE if too small).  tile_masks,
  * when not NULL, receives up to max_passes 64-bit masks of each pass's tile qubits. */
 int qsv_plan_debug(const qsv_circuit* c, int32_t tile_qubits, int32_t* order, int32_t* pass_of,
-                   int32_t* n_passes, uint64_t* tile_masks, int32_t max_passes);
+                   int32_t max_entries, int32_t* n_entries, int32_t* n_passes, uint64_t* tile_masks,
+                   int32_t max_passes);
 
 #ifdef __cplusplus
 }

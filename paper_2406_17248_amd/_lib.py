@@ -117,8 +117,8 @@ def lib():
             "qsv_param_shift_grad_batch": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), dp, sz, sz,
                                             dp, dp], C.c_int),
             "qsv_profile_read": ([vp, i32, dp, C.POINTER(i64), dp], C.c_int),
-            "qsv_plan_debug": ([C.POINTER(qsv_circuit), i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
-                                C.POINTER(C.c_uint64), i32], C.c_int),
+            "qsv_plan_debug": ([C.POINTER(qsv_circuit), i32, C.POINTER(i32), C.POINTER(i32), i32, C.POINTER(i32),
+                                C.POINTER(i32), C.POINTER(C.c_uint64), i32], C.c_int),
         }
         for name, (args, res) in sigs.items():
             f = getattr(L, name)
@@ -377,12 +377,15 @@ def qsv_profile_read(s, kernel_class):
 
 
 def qsv_plan_debug(circuit, tile_qubits):
+    """(gate index per executed primitive, pass of each, number of passes, tile masks)."""
     c = _circuit(circuit)
-    n = int(c.c.n_gates)
-    order = (C.c_int32 * max(n, 1))()
-    pass_of = (C.c_int32 * max(n, 1))()
-    n_passes = C.c_int32()
-    masks = (C.c_uint64 * max(n, 1))()
-    check(lib().qsv_plan_debug(c.ptr, int(tile_qubits), order, pass_of, C.byref(n_passes), masks, max(n, 1)))
-    return (np.array(order[:n]), np.array(pass_of[:n]), int(n_passes.value),
+    cap = max(5 * int(c.c.n_gates), 1)
+    order = (C.c_int32 * cap)()
+    pass_of = (C.c_int32 * cap)()
+    n_entries, n_passes = C.c_int32(), C.c_int32()
+    masks = (C.c_uint64 * cap)()
+    check(lib().qsv_plan_debug(c.ptr, int(tile_qubits), order, pass_of, cap, C.byref(n_entries),
+                               C.byref(n_passes), masks, cap))
+    k = n_entries.value
+    return (np.array(order[:k]), np.array(pass_of[:k]), int(n_passes.value),
             np.array(masks[:n_passes.value], dtype=np.uint64))

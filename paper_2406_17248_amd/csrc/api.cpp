@@ -147,14 +147,20 @@ void stage_release_after_queue(qsv_state* s) {
 // Default options per dtype.
 void default_options(qsv_state* s) {
   s->opt[QSV_OPT_TILE_QUBITS] = s->dtype == QSV_C64 ? 13 : 12;
-  s->opt[QSV_OPT_ADJ_TILE_QUBITS] = s->dtype == QSV_C64 ? 12 : 11;
+  s->opt[QSV_OPT_ADJ_TILE_QUBITS] = s->dtype == QSV_C64 ? 13 : 12;
   s->opt[QSV_OPT_THREADS] = 512;
 }
 
 PlanOptions plan_options(const qsv_state* s, bool adjoint, bool fuse_zz) {
   PlanOptions o;
   o.tile_qubits = (int32_t)(adjoint ? s->opt[QSV_OPT_ADJ_TILE_QUBITS] : s->opt[QSV_OPT_TILE_QUBITS]);
-  if (adjoint && o.tile_qubits == 0) o.tile_qubits = s->dtype == QSV_C64 ? 12 : 11;
+  if (adjoint && o.tile_qubits == 0) o.tile_qubits = s->dtype == QSV_C64 ? 13 : 12;
+  // complex128 adjoint tiles above 12 qubits would spill registers at 1024 threads
+  if (adjoint && s->dtype == QSV_C128) o.tile_qubits = std::min(o.tile_qubits, 12);
+  // tiles below the register-blocked range use the LDS-sweep kernel, whose adjoint
+  // variant stages psi and lambda together
+  if (rb_capacity_host(s->dtype, std::min<int>(o.tile_qubits, s->n)) < 0)
+    o.tile_qubits = std::min<int>(o.tile_qubits, adjoint ? (s->dtype == QSV_C64 ? 12 : 11) : 13);
   o.low_qubits = s->dtype == QSV_C64 ? 4 : 3;
   o.fuse_zz = fuse_zz;
   o.dtype = s->dtype;
@@ -177,7 +183,7 @@ const Plan& get_plan(qsv_state* s, const qsv_circuit* c, bool adjoint, bool fuse
 struct Uploaded {
   TileOp* ops = nullptr;
   DiagEntry* diag = nullptr;
-  int32_t* edges = nullptr;
+  ZZEdge* edges = nullptr;
   void* ctab = nullptr;
   int64_t ctab_stride = 0;  // complex entries per batch item
 };
@@ -197,7 +203,7 @@ void upload_plans(qsv_state* s, const UploadReq* reqs, int n_req, Uploaded* out)
     const Plan& p = *reqs[r].plan;
     o_ops[r] = off; off = align_up(off + p.ops.size() * sizeof(TileOp), 256);
     o_diag[r] = off; off = align_up(off + p.diag.size() * sizeof(DiagEntry), 256);
-    o_edges[r] = off; off = align_up(off + p.edges.size() * sizeof(int32_t), 256);
+    o_edges[r] = off; off = align_up(off + p.edges.size() * sizeof(ZZEdge), 256);
     o_ctab[r] = off; off = align_up(off + (size_t)reqs[r].batch * p.ctab_size * cs, 256);
   }
   const size_t total = off ? off : 256;
@@ -206,7 +212,7 @@ void upload_plans(qsv_state* s, const UploadReq* reqs, int n_req, Uploaded* out)
     const Plan& p = *reqs[r].plan;
     if (!p.ops.empty()) std::memcpy(st + o_ops[r], p.ops.data(), p.ops.size() * sizeof(TileOp));
     if (!p.diag.empty()) std::memcpy(st + o_diag[r], p.diag.data(), p.diag.size() * sizeof(DiagEntry));
-    if (!p.edges.empty()) std::memcpy(st + o_edges[r], p.edges.data(), p.edges.size() * sizeof(int32_t));
+    if (!p.edges.empty()) std::memcpy(st + o_edges[r], p.edges.data(), p.edges.size() * sizeof(ZZEdge));
     const std::vector<cplx>& ct = *reqs[r].ctab;
     const size_t ne = (size_t)reqs[r].batch * p.ctab_size;
     if (s->dtype == QSV_C64) {
@@ -224,10 +230,17 @@ void upload_plans(qsv_state* s, const UploadReq* reqs, int n_req, Uploaded* out)
   for (int r = 0; r < n_req; ++r) {
     out[r].ops = reinterpret_cast<TileOp*>(d + o_ops[r]);
     out[r].diag = reinterpret_cast<DiagEntry*>(d + o_diag[r]);
-    out[r].edges = reinterpret_cast<int32_t*>(d + o_edges[r]);
+    out[r].edges = reinterpret_cast<ZZEdge*>(d + o_edges[r]);
     out[r].ctab = d + o_ctab[r];
     out[r].ctab_stride = reqs[r].plan->ctab_size;
   }
+}
+
+hipError_t launch_pass(const qsv_state* s, const DevPass& dp, PassArgs A, int batch, bool adj) {
+  A.lr0 = dp.lr0;
+  const uint64_t tiles = 1ull << (s->n - dp.m);
+  if (dp.rb) return launch_tile_pass_rb(s->dtype, adj, dp.maxm, A, tiles, batch, s->stream);
+  return launch_tile_pass(s->dtype, adj, dp.maxm, A, tiles, batch, s->stream);
 }
 
 // Run a forward plan on batch states.  src (may equal psi) is read by the first pass with
@@ -281,7 +294,7 @@ void run_forward(qsv_state* s, const Plan& p, const Uploaded& u, void* psi, int6
     A.n_pslots = 0;
     const double bytes = 2.0 * (double)batch * (double)s->namps() * (double)s->amp_bytes();
     timed(s, QSV_K_TILE_FORWARD, bytes,
-          [&] { return launch_tile_pass(s->dtype, false, dp.maxm, A, 1ull << (n - dp.m), batch, s->stream); },
+          [&] { return launch_pass(s, dp, A, batch, false); },
           "tile pass");
     first = false;
   }
@@ -431,7 +444,7 @@ void energies_and_grads(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum*
       A.n_pslots = P;
       const double bytes = 4.0 * (double)batch * (double)s->namps() * (double)s->amp_bytes();
       timed(s, QSV_K_TILE_ADJOINT, bytes,
-            [&] { return launch_tile_pass(s->dtype, true, ap.maxm, A, 1ull << (s->n - ap.m), batch, s->stream); },
+            [&] { return launch_pass(s, ap, A, batch, true); },
             "adjoint tile pass");
     }
     hip_check(launch_reduce_columns(static_cast<double*>(s->gpart.p), (int64_t)tiles, (int64_t)ng, d_out + ne,
@@ -611,11 +624,10 @@ int qsv_state_set_option(qsv_state* s, int32_t option, int64_t value) {
     check_state(s);
     if (option < 0 || option >= QSV_OPT_COUNT) fail(QSV_EINVAL, "unknown option");
     if (option == QSV_OPT_TILE_QUBITS) {
-      if (value != 0 && (value < 2 || tile_capacity_host(s->dtype, false, (int)value) < 0))
-        fail(QSV_EINVAL, "tile width must be 0 or fit in LDS (c64 <= 14, c128 <= 13)");
+      if (value != 0 && (value < 2 || value > 13))
+        fail(QSV_EINVAL, "tile width must be 0 (per-gate kernels) or in [2, 13]");
     } else if (option == QSV_OPT_ADJ_TILE_QUBITS) {
-      if (value < 2 || tile_capacity_host(s->dtype, true, (int)value) < 0)
-        fail(QSV_EINVAL, "adjoint tile width must fit psi and lambda in LDS (c64 <= 13, c128 <= 12)");
+      if (value < 2 || value > 13) fail(QSV_EINVAL, "adjoint tile width must be in [2, 13]");
     } else if (option == QSV_OPT_THREADS) {
       if (value != 256 && value != 512 && value != 1024) fail(QSV_EINVAL, "threads must be 256, 512 or 1024");
     } else if (option == QSV_OPT_PROFILE) {
@@ -809,15 +821,17 @@ int qsv_profile_read(qsv_state* s, int32_t kernel_class, double* total_ms, int64
   });
 }
 
-int qsv_plan_debug(const qsv_circuit* c, int32_t tile_qubits, int32_t* order, int32_t* pass_of, int32_t* n_passes,
-                   uint64_t* tile_masks, int32_t max_passes) {
+int qsv_plan_debug(const qsv_circuit* c, int32_t tile_qubits, int32_t* order, int32_t* pass_of,
+                   int32_t max_entries, int32_t* n_entries, int32_t* n_passes, uint64_t* tile_masks,
+                   int32_t max_passes) {
   return guarded([&] {
     validate_circuit(c, (size_t)1 << 30, -1);
-    if (!order || !pass_of || !n_passes) fail(QSV_EINVAL, "output arrays are NULL");
+    if (!order || !pass_of || !n_passes || !n_entries) fail(QSV_EINVAL, "output arrays are NULL");
     if (tile_qubits < 2 || tile_qubits > 34) fail(QSV_EINVAL, "tile_qubits must be in [2, 34]");
     const std::vector<Prim> prims = lower_forward(c);
+    if ((int64_t)prims.size() > max_entries) fail(QSV_ERANGE, "order / pass_of arrays are too small");
     const std::vector<Pass> passes = plan_passes(prims, c->n_qubits, std::min(tile_qubits, c->n_qubits), 3);
-    size_t k = 0;
+    int32_t k = 0;
     for (size_t p = 0; p < passes.size(); ++p) {
       for (int32_t i : passes[p].prims) {
         order[k] = prims[i].gate;
@@ -826,6 +840,7 @@ int qsv_plan_debug(const qsv_circuit* c, int32_t tile_qubits, int32_t* order, in
       }
       if (tile_masks && (int32_t)p < max_passes) tile_masks[p] = passes[p].tile_mask;
     }
+    *n_entries = k;
     *n_passes = (int32_t)passes.size();
   });
 }

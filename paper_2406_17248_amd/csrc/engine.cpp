@@ -182,6 +182,23 @@ int prim_numbers(const Prim& p, const qsv_circuit* c, const double* ang, cplx* o
       cnt = 4;
       break;
     case M_CPHASE_HALF: out[0] = std::polar(1.0, a / 2); out[1] = out[0]; cnt = 2; break;
+    case M_H: {
+      const double r = std::sqrt(0.5);
+      out[0] = r; out[1] = r; out[2] = r; out[3] = -r; cnt = 4;
+      break;
+    }
+    case M_RX_PLUS: case M_RX_MINUS: {
+      const double r = std::sqrt(0.5);
+      const double sg = p.recipe == M_RX_PLUS ? 1.0 : -1.0;
+      out[0] = r; out[1] = -I1 * r * sg; out[2] = -I1 * r * sg; out[3] = r; cnt = 4;
+      break;
+    }
+    case M_ZZ_ANGLE: {
+      const double h = 0.5 * ang[0];
+      out[0] = std::polar(1.0, -h); out[1] = std::polar(1.0, h); out[2] = std::polar(1.0, h); out[3] = std::polar(1.0, -h);
+      cnt = 4;
+      break;
+    }
     default: return 0;
   }
   if (p.dagger) dagger_numbers(p.type, out, cnt);
@@ -271,10 +288,56 @@ void validate_pauli_sum(const qsv_pauli_sum* h, int32_t n) {
 }
 
 // ---- lowering -------------------------------------------------------------------------------
+// RXX(t) = (H x H) RZZ(t) (H x H) and RYY(t) = RX(-pi/2)^2 RZZ(t) RX(pi/2)^2 (operator
+// order), so both become one-qubit basis changes around a diagonal RZZ; with controls only
+// the RZZ part is controlled.  Forward order of the parts.
+static std::vector<Prim> lower_pauli_pair(const qsv_circuit* c, int i) {
+  const qsv_gate& g = c->gates[i];
+  const bool xx = g.kind == QSV_GATE_RXX;
+  std::vector<Prim> parts;
+  auto basis = [&](int q, int recipe) {
+    Prim p{};
+    p.type = P_DENSE1;
+    p.gate = i;
+    p.q0 = q;
+    p.q1 = -1;
+    p.cmask = 0;
+    p.recipe = recipe;
+    p.param = -1;
+    p.gen = G_NONE;
+    finish_masks(p);
+    parts.push_back(p);
+  };
+  const int pre = xx ? M_H : M_RX_PLUS, post = xx ? M_H : M_RX_MINUS;
+  basis(g.targets[0], pre);
+  basis(g.targets[1], pre);
+  Prim z{};
+  z.type = P_DIAG2;
+  z.gate = i;
+  z.q0 = g.targets[0];
+  z.q1 = g.targets[1];
+  z.cmask = g.ctrl_mask;
+  z.recipe = M_ZZ_ANGLE;
+  z.param = -1;
+  z.gen = G_NONE;
+  finish_masks(z);
+  parts.push_back(z);
+  basis(g.targets[0], post);
+  basis(g.targets[1], post);
+  return parts;
+}
+
 std::vector<Prim> lower_forward(const qsv_circuit* c) {
   std::vector<Prim> out;
   out.reserve(c->n_gates);
-  for (size_t i = 0; i < c->n_gates; ++i) out.push_back(forward_prim(c, (int)i));
+  for (size_t i = 0; i < c->n_gates; ++i) {
+    const int k = c->gates[i].kind;
+    if (k == QSV_GATE_RXX || k == QSV_GATE_RYY) {
+      for (const Prim& p : lower_pauli_pair(c, (int)i)) out.push_back(p);
+    } else {
+      out.push_back(forward_prim(c, (int)i));
+    }
+  }
   return out;
 }
 
@@ -310,6 +373,20 @@ std::vector<Prim> lower_adjoint(const qsv_circuit* c) {
         p.gen = pi >= 0 ? parts[k].gen : G_NONE;
         p.coeff = pi >= 0 ? parts[k].scale * g.param_coeff[parts[k].slot] : 0.0;
         finish_masks(p);
+        out.push_back(p);
+      }
+      continue;
+    }
+    if (g.kind == QSV_GATE_RXX || g.kind == QSV_GATE_RYY) {
+      std::vector<Prim> parts = lower_pauli_pair(c, i);
+      for (int k = (int)parts.size() - 1; k >= 0; --k) {
+        Prim p = parts[k];
+        p.dagger = true;
+        if (p.recipe == M_ZZ_ANGLE && g.param_index[0] >= 0) {
+          p.gen = G_ZZ;
+          p.param = g.param_index[0];
+          p.coeff = g.param_coeff[0];
+        }
         out.push_back(p);
       }
       continue;
@@ -434,6 +511,235 @@ static bool zz_fusable(const Prim& p, const qsv_circuit* c) {
   return p.recipe == M_GATE && p.cmask == 0 && c->gates[p.gate].kind == QSV_GATE_RZZ;
 }
 
+int rb_capacity_host(int dtype, int m) {
+  if (m < kRegBits + 6 || m > 13) return -1;
+  const size_t amp = dtype == 0 ? 8 : 16;
+  return amp * ((size_t)1 << m) <= 131072 ? m : -1;
+}
+
+std::vector<Pass> plan_rounds(const std::vector<Prim>& prims, const std::vector<int32_t>& seq, uint64_t allowed,
+                              int32_t r) {
+  // Same greedy as plan_passes, but only one-qubit dense primitives need register
+  // qubits (two-qubit dense ones run through LDS, diagonal ones are elementwise).
+  std::vector<Pass> rounds;
+  std::vector<int32_t> rem = seq;
+  auto need = [&](const Prim& p) { return p.type == P_DENSE1 ? p.nondiag : 0ull; };
+  auto sched = [&](uint64_t R, std::vector<int32_t>* out, std::vector<int32_t>* left, int* n_dense) {
+    uint64_t blocked_any = 0, blocked_nd = 0;
+    int dense = 0;
+    for (int32_t i : rem) {
+      const Prim& p = prims[i];
+      const bool ok = (need(p) & ~R) == 0 && (p.nondiag & blocked_any) == 0 &&
+                      ((p.touched & ~p.nondiag) & blocked_nd) == 0;
+      if (ok) {
+        if (out) out->push_back(i);
+        if (need(p)) ++dense;
+      } else {
+        if (left) left->push_back(i);
+        blocked_any |= p.touched;
+        blocked_nd |= p.nondiag;
+      }
+    }
+    if (n_dense) *n_dense = dense;
+  };
+  while (!rem.empty()) {
+    std::vector<int> first_need(64, 1 << 30);
+    for (size_t k = 0; k < rem.size(); ++k) {
+      uint64_t nd = need(prims[rem[k]]);
+      while (nd) {
+        const int q = __builtin_ctzll(nd);
+        if (first_need[q] > (int)k) first_need[q] = (int)k;
+        nd &= nd - 1;
+      }
+    }
+    uint64_t R = 0;
+    while (popc(R) < r) {
+      int best_q = -1, best_dense = -1, best_first = 1 << 30;
+      for (int q = 0; q < 64; ++q) {
+        if (!(allowed >> q & 1) || (R >> q & 1)) continue;
+        int dense = 0;
+        sched(R | (1ull << q), nullptr, nullptr, &dense);
+        if (dense > best_dense || (dense == best_dense && first_need[q] < best_first)) {
+          best_q = q;
+          best_dense = dense;
+          best_first = first_need[q];
+        }
+      }
+      if (best_q < 0) break;
+      R |= 1ull << best_q;
+    }
+    Pass rd;
+    std::vector<int32_t> left;
+    sched(R, &rd.prims, &left, nullptr);
+    if (rd.prims.empty()) {
+      R = need(prims[rem[0]]);
+      for (int q = 0; popc(R) < r && q < 64; ++q)
+        if (allowed >> q & 1) R |= 1ull << q;
+      rd.prims.clear();
+      left.clear();
+      sched(R, &rd.prims, &left, nullptr);
+    }
+    rd.tile_mask = R;
+    rd.m = popc(R);
+    rounds.push_back(rd);
+    rem.swap(left);
+  }
+  return rounds;
+}
+
+namespace {
+
+struct PassEmitter {
+  Plan& plan;
+  const qsv_circuit* c;
+  bool adjoint;
+  const PlanOptions& opt;
+  uint64_t T;
+  int loc[64];
+  std::vector<int32_t> op_param;  // gradient parameter of each op of the pass (-1 none)
+
+  int alloc(int count) {
+    const int off = plan.ctab_size;
+    plan.ctab_size += count;
+    return off;
+  }
+  uint32_t local_mask(uint64_t gm) const {
+    uint32_t lm = 0;
+    while (gm) {
+      const int q = __builtin_ctzll(gm);
+      lm |= 1u << loc[q];
+      gm &= gm - 1;
+    }
+    return lm;
+  }
+  void push(const TileOp& op, int32_t param) {
+    plan.ops.push_back(op);
+    op_param.push_back(param);
+  }
+  void remap(int32_t lr) {
+    TileOp op{};
+    op.type = OP_REMAP;
+    op.a = lr;
+    for (int bit = 0, sh = 0; bit < 32; ++bit)
+      if (lr >> bit & 1) { op.b |= bit << sh; sh += 8; }
+    op.gen = -1;
+    op.pslot = -1;
+    push(op, -1);
+  }
+  // Emit ops for primitives seq (in order).  reg_index: for register-blocked passes the
+  // register index of each local bit (-1 if not a register bit), else nullptr.
+  void emit(const std::vector<int32_t>& seq, const int* reg_index) {
+    size_t k = 0;
+    while (k < seq.size()) {
+      const Prim& p = plan.prims[seq[k]];
+      TileOp op{};
+      op.gen = -1;
+      op.pslot = -1;
+      op.flush = 0;
+      if (p.type == P_DENSE1 || p.type == P_DENSE2) {
+        op.type = p.type == P_DENSE1 ? OP_DENSE1 : OP_DENSE2;
+        if (p.type == P_DENSE1 && reg_index) {
+          op.a = reg_index[loc[p.q0]];
+          if (op.a < 0) fail(QSV_EINVAL, "internal: dense target is not a register bit");
+        } else {
+          op.a = loc[p.q0];
+          op.b = p.type == P_DENSE2 ? loc[p.q1] : 0;
+        }
+        op.lmask = local_mask(p.cmask & T);
+        op.omask = p.cmask & ~T;
+        op.mat = alloc(prim_size(p));
+        plan.fills.push_back({F_PRIM_MATRIX, seq[k], 0, op.mat});
+        int32_t prm = -1;
+        if (adjoint && p.gen != G_NONE) {
+          if (reg_index && p.type == P_DENSE2) fail(QSV_EINVAL, "internal: gradient on an LDS two-qubit op");
+          op.gen = alloc(prim_size(p));
+          plan.fills.push_back({F_PRIM_GEN, seq[k], 0, op.gen});
+          prm = p.param;
+        }
+        push(op, prm);
+        ++k;
+        continue;
+      }
+      if (opt.fuse_zz && zz_fusable(p, c)) {
+        size_t e = k + 1;
+        while (e < seq.size() && zz_fusable(plan.prims[seq[e]], c) &&
+               same_binding(c->gates[plan.prims[seq[e]].gate], c->gates[p.gate]) &&
+               plan.prims[seq[e]].param == p.param && plan.prims[seq[e]].coeff == p.coeff)
+          ++e;
+        if (e - k >= 2) {
+          op.type = OP_ZZ;
+          op.first = (int32_t)plan.edges.size();
+          op.count = (int32_t)(e - k);
+          for (size_t r = k; r < e; ++r) {
+            const int u = plan.prims[seq[r]].q0, v = plan.prims[seq[r]].q1;
+            plan.edges.push_back(ZZEdge{u, v, loc[u], loc[v]});
+          }
+          op.mat = alloc(op.count + 1);
+          plan.fills.push_back({F_ZZ_PHASES, seq[k], op.count, op.mat});
+          if (adjoint && p.gen != G_NONE) {
+            op.gen = alloc(op.count + 1);
+            plan.fills.push_back({F_ZZ_GEN, seq[k], op.count, op.gen});
+          }
+          push(op, adjoint && p.gen != G_NONE ? p.param : -1);
+          k = e;
+          continue;
+        }
+      }
+      op.type = OP_DIAG;
+      op.first = (int32_t)plan.diag.size();
+      int32_t run_param = -1;
+      size_t e = k;
+      while (e < seq.size()) {
+        const Prim& q = plan.prims[seq[e]];
+        if (!(q.type == P_DIAG1 || q.type == P_DIAG2 || q.type == P_SIGN)) break;
+        if (e > k && opt.fuse_zz && zz_fusable(q, c) && e + 1 < seq.size() &&
+            zz_fusable(plan.prims[seq[e + 1]], c) &&
+            same_binding(c->gates[plan.prims[seq[e + 1]].gate], c->gates[q.gate]))
+          break;  // let the ZZ run start its own op
+        const int32_t qp = (adjoint && q.gen != G_NONE) ? q.param : -1;
+        if (qp >= 0) {
+          if (run_param >= 0 && qp != run_param) break;
+          run_param = qp;
+        }
+        DiagEntry d{};
+        d.kind = q.type == P_SIGN ? DIAG_SIGN : DIAG_PHASE;
+        d.q0 = q.q0;
+        d.q1 = q.type == P_DIAG2 ? q.q1 : -1;
+        d.cmask = q.cmask;
+        d.l0 = loc[d.q0];
+        d.l1 = d.q1 >= 0 ? loc[d.q1] : -1;
+        d.lcmask = local_mask(q.cmask & T);
+        d.ocmask = q.cmask & ~T;
+        d.mat = -1;
+        d.gen = -1;
+        if (q.type != P_SIGN) {
+          d.mat = alloc(prim_size(q));
+          plan.fills.push_back({F_PRIM_MATRIX, seq[e], 0, d.mat});
+        }
+        if (qp >= 0) {
+          d.gen = alloc(prim_size(q));
+          plan.fills.push_back({F_PRIM_GEN, seq[e], 0, d.gen});
+        }
+        plan.diag.push_back(d);
+        ++e;
+      }
+      op.count = (int32_t)(plan.diag.size() - op.first);
+      push(op, run_param);
+      k = e;
+    }
+  }
+};
+
+// A local register mask of exactly r bits containing the round's register qubits,
+// padded with the highest free local bits (away from the coalescing bits).
+int32_t round_layout(const PassEmitter& em, uint64_t round_mask, int m, int r) {
+  int32_t lr = (int32_t)em.local_mask(round_mask);
+  for (int bit = m - 1; bit >= 0 && popc((uint64_t)lr) < r; --bit) lr |= 1 << bit;
+  return lr;
+}
+
+}  // namespace
+
 Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
   Plan plan;
   plan.adjoint = adjoint;
@@ -463,6 +769,9 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
         d.mat = mat;
         d.cmask = p.cmask;
         d.gen = -1;
+        d.l0 = d.l1 = -1;
+        d.lcmask = 0;
+        d.ocmask = 0;
         de = (int)plan.diag.size();
         plan.diag.push_back(d);
       }
@@ -473,132 +782,62 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
   }
 
   const int m = std::min<int>(std::max(opt.tile_qubits, 2), n);
-  const int maxm = tile_capacity_host(opt.dtype, adjoint, m);
+  const bool rb = opt.use_rb && rb_capacity_host(opt.dtype, m) >= 0;
+  const int maxm = rb ? m : tile_capacity_host(opt.dtype, adjoint, m);
   if (maxm < 0) fail(QSV_EINVAL, "tile width does not fit in LDS for this dtype");
   const std::vector<Pass> passes = plan_passes(plan.prims, n, m, opt.low_qubits);
+  const int low_local = std::max(0, std::min(opt.low_qubits, m - 2));
+  const int32_t low_mask = (1 << low_local) - 1;
   for (const Pass& ps : passes) {
     DevPass dp{};
     dp.tile_mask = ps.tile_mask;
     dp.m = ps.m;
     dp.maxm = maxm;
+    dp.rb = rb ? 1 : 0;
     dp.op_first = (int32_t)plan.ops.size();
     dp.pslot_first = plan.n_pslots;
-    int loc[64];
+    PassEmitter em{plan, c, adjoint, opt, ps.tile_mask, {}, {}};
     {
       int r = 0;
-      for (int q = 0; q < 64; ++q) loc[q] = (ps.tile_mask >> q & 1) ? r++ : -1;
+      for (int q = 0; q < 64; ++q) em.loc[q] = (ps.tile_mask >> q & 1) ? r++ : -1;
     }
-    auto local_mask = [&](uint64_t gm) {
-      uint32_t lm = 0;
-      while (gm) {
-        const int q = __builtin_ctzll(gm);
-        lm |= 1u << loc[q];
-        gm &= gm - 1;
+    if (!rb) {
+      em.emit(ps.prims, nullptr);
+    } else {
+      const int r = kRegBits;
+      const std::vector<Pass> rounds = plan_rounds(plan.prims, ps.prims, ps.tile_mask, r);
+      const int32_t top = ((1 << r) - 1) << (ps.m - r);  // load/store layout
+      int32_t cur = -1;
+      for (size_t ri = 0; ri < rounds.size(); ++ri) {
+        bool has_dense = false;
+        for (int32_t i : rounds[ri].prims) has_dense |= plan.prims[i].type == P_DENSE1;
+        const int32_t lr = round_layout(em, rounds[ri].tile_mask, ps.m, r);
+        if (cur < 0) {
+          // first round: load straight into its layout when the coalescing bits stay thread bits
+          cur = (has_dense && (lr & low_mask) == 0) ? lr : top;
+          dp.lr0 = cur;
+        }
+        if (has_dense && lr != cur) {
+          em.remap(lr);
+          cur = lr;
+        }
+        int reg_index[32];
+        for (int bit = 0, ri2 = 0; bit < 32; ++bit) reg_index[bit] = (cur >> bit & 1) ? ri2++ : -1;
+        em.emit(rounds[ri].prims, reg_index);
       }
-      return lm;
-    };
-    std::vector<int32_t> op_param;  // gradient parameter of each op of this pass (-1 none)
-    const std::vector<int32_t>& seq = ps.prims;
-    size_t k = 0;
-    while (k < seq.size()) {
-      const Prim& p = plan.prims[seq[k]];
-      TileOp op{};
-      op.gen = -1;
-      op.pslot = -1;
-      op.flush = 0;
-      if (p.type == P_DENSE1 || p.type == P_DENSE2) {
-        op.type = p.type == P_DENSE1 ? OP_DENSE1 : OP_DENSE2;
-        op.a = loc[p.q0];
-        op.b = p.type == P_DENSE2 ? loc[p.q1] : 0;
-        op.lmask = local_mask(p.cmask & ps.tile_mask);
-        op.omask = p.cmask & ~ps.tile_mask;
-        op.mat = alloc(prim_size(p));
-        plan.fills.push_back({F_PRIM_MATRIX, seq[k], 0, op.mat});
-        if (adjoint && p.gen != G_NONE) {
-          op.gen = alloc(prim_size(p));
-          plan.fills.push_back({F_PRIM_GEN, seq[k], 0, op.gen});
-        }
-        plan.ops.push_back(op);
-        op_param.push_back(adjoint && p.gen != G_NONE ? p.param : -1);
-        ++k;
-        continue;
-      }
-      // diagonal primitives: a fused ZZ run, or a run of diagonal entries
-      if (opt.fuse_zz && zz_fusable(p, c)) {
-        size_t e = k + 1;
-        while (e < seq.size() && zz_fusable(plan.prims[seq[e]], c) &&
-               same_binding(c->gates[plan.prims[seq[e]].gate], c->gates[p.gate]) &&
-               plan.prims[seq[e]].param == p.param && plan.prims[seq[e]].coeff == p.coeff)
-          ++e;
-        if (e - k >= 2) {
-          op.type = OP_ZZ;
-          op.first = (int32_t)(plan.edges.size() / 2);
-          op.count = (int32_t)(e - k);
-          for (size_t r = k; r < e; ++r) {
-            plan.edges.push_back(plan.prims[seq[r]].q0);
-            plan.edges.push_back(plan.prims[seq[r]].q1);
-          }
-          op.mat = alloc(op.count + 1);
-          plan.fills.push_back({F_ZZ_PHASES, seq[k], op.count, op.mat});
-          if (adjoint && p.gen != G_NONE) {
-            op.gen = alloc(op.count + 1);
-            plan.fills.push_back({F_ZZ_GEN, seq[k], op.count, op.gen});
-          }
-          plan.ops.push_back(op);
-          op_param.push_back(adjoint && p.gen != G_NONE ? p.param : -1);
-          k = e;
-          continue;
-        }
-      }
-      op.type = OP_DIAG;
-      op.first = (int32_t)plan.diag.size();
-      int32_t run_param = -1;
-      size_t e = k;
-      while (e < seq.size()) {
-        const Prim& q = plan.prims[seq[e]];
-        if (!(q.type == P_DIAG1 || q.type == P_DIAG2 || q.type == P_SIGN)) break;
-        if (e > k && opt.fuse_zz && zz_fusable(q, c) && e + 1 < seq.size() &&
-            zz_fusable(plan.prims[seq[e + 1]], c) &&
-            same_binding(c->gates[plan.prims[seq[e + 1]].gate], c->gates[q.gate]))
-          break;  // let the ZZ run start its own op
-        const int32_t qp = (adjoint && q.gen != G_NONE) ? q.param : -1;
-        if (qp >= 0) {
-          if (run_param >= 0 && qp != run_param) break;
-          run_param = qp;
-        }
-        DiagEntry d{};
-        d.kind = q.type == P_SIGN ? DIAG_SIGN : DIAG_PHASE;
-        d.q0 = q.q0;
-        d.q1 = q.type == P_DIAG2 ? q.q1 : -1;
-        d.cmask = q.cmask;
-        d.mat = -1;
-        d.gen = -1;
-        if (q.type != P_SIGN) {
-          d.mat = alloc(prim_size(q));
-          plan.fills.push_back({F_PRIM_MATRIX, seq[e], 0, d.mat});
-        }
-        if (qp >= 0) {
-          d.gen = alloc(prim_size(q));
-          plan.fills.push_back({F_PRIM_GEN, seq[e], 0, d.gen});
-        }
-        plan.diag.push_back(d);
-        ++e;
-      }
-      op.count = (int32_t)(plan.diag.size() - op.first);
-      plan.ops.push_back(op);
-      op_param.push_back(run_param);
-      k = e;
+      if (cur < 0) dp.lr0 = cur = top;
+      if (cur & low_mask) em.remap(top);
     }
     // gradient slots: consecutive ops of one parameter share an accumulator
     if (adjoint) {
-      int32_t cur = -1, last_op = -1, local = -1;
-      for (size_t i = 0; i < op_param.size(); ++i) {
-        const int32_t prm = op_param[i];
+      int32_t cur_p = -1, last_op = -1, local = -1;
+      for (size_t i = 0; i < em.op_param.size(); ++i) {
+        const int32_t prm = em.op_param[i];
         if (prm < 0) continue;
         TileOp& o = plan.ops[dp.op_first + i];
-        if (prm != cur) {
+        if (prm != cur_p) {
           if (last_op >= 0) plan.ops[last_op].flush = 1;
-          cur = prm;
+          cur_p = prm;
           ++local;
           plan.pslot_param.push_back(prm);
         }
@@ -618,8 +857,8 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
 std::string structure_key(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
   std::string key;
   auto put = [&](const void* p, size_t n) { key.append(reinterpret_cast<const char*>(p), n); };
-  const int32_t head[6] = {c->n_qubits, adjoint ? 1 : 0, opt.tile_qubits, opt.low_qubits, opt.fuse_zz ? 1 : 0,
-                           opt.dtype};
+  const int32_t head[7] = {c->n_qubits, adjoint ? 1 : 0, opt.tile_qubits, opt.low_qubits, opt.fuse_zz ? 1 : 0,
+                           opt.dtype, opt.use_rb ? 1 : 0};
   put(head, sizeof(head));
   for (size_t i = 0; i < c->n_gates; ++i) {
     const qsv_gate& g = c->gates[i];

@@ -34,6 +34,10 @@ enum MatRecipe : int32_t {
   M_RY_ANGLE,    // RY(angle[angle_slot])
   M_CPHASE_HALF, // exp(i angle[angle_slot] / 2) on the control subspace
   M_SIGN,        // no numbers (sign flip)
+  M_H,           // Hadamard (basis change of a lowered RXX)
+  M_RX_PLUS,     // RX(+pi/2) (basis change of a lowered RYY)
+  M_RX_MINUS,    // RX(-pi/2)
+  M_ZZ_ANGLE,    // diag(e^{-i a/2}, e^{i a/2}, e^{i a/2}, e^{-i a/2}), a = angle[0]
 };
 
 enum PrimType : int32_t { P_DENSE1 = 0, P_DENSE2, P_DIAG1, P_DIAG2, P_SIGN };
@@ -78,6 +82,8 @@ struct DevPass {
   uint64_t tile_mask;
   int32_t  m;
   int32_t  maxm;       // LDS capacity instantiation
+  int32_t  rb;         // 1: register-blocked kernel (3 register bits)
+  int32_t  lr0;        // register-blocked: local register mask at load time
   int32_t  op_first, op_count;
   int32_t  pslot_first, pslot_count;
 };
@@ -91,7 +97,7 @@ struct Plan {
   std::vector<DevPass> passes;
   std::vector<TileOp> ops;
   std::vector<DiagEntry> diag;
-  std::vector<int32_t> edges;
+  std::vector<ZZEdge> edges;
   std::vector<Fill> fills;
   int32_t ctab_size = 0;            // complex entries per batch item
   std::vector<int32_t> pslot_param; // adjoint: parameter of each gradient slot
@@ -106,6 +112,7 @@ struct PlanOptions {
   int32_t low_qubits = 3;     // always in the tile (coalescing)
   bool    fuse_zz = true;     // fuse runs of equally-bound RZZ into one phase-table op
   int32_t dtype = 1;
+  bool    use_rb = true;      // register-blocked kernel for tiles of 9..13 qubits
 };
 
 // Validate a circuit against n_params (and the state's n).  Throws Error.
@@ -124,6 +131,15 @@ std::vector<Pass> plan_passes(const std::vector<Prim>& prims, int32_t n, int32_t
 // Smallest LDS tile instantiation (in qubits) holding 2^m amplitudes of each staged state
 // (one for forward passes, psi and lambda for the adjoint) within 128 KiB, or -1.
 int tile_capacity_host(int dtype, bool adj, int m);
+
+// Register-blocked passes: 3 register bits; used for tiles of 9..13 qubits within 128 KiB.
+constexpr int kRegBits = 3;
+int rb_capacity_host(int dtype, int m);
+
+// Register rounds of one register-blocked pass: groups of the pass's primitives whose
+// one-qubit dense targets fit in r register qubits (drawn from `allowed`).
+std::vector<Pass> plan_rounds(const std::vector<Prim>& prims, const std::vector<int32_t>& seq, uint64_t allowed,
+                              int32_t r);
 
 // Full plan (passes + device op lists + binding recipe).
 Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt);

@@ -9,6 +9,10 @@ namespace qsv {
 
 hipError_t launch_tile_pass(int dtype, bool adj, int maxm, const PassArgs& A, uint64_t n_tiles,
                             int batch, hipStream_t s);
+// Register-blocked tile pass (3 register bits, 2^(maxm-3) threads, 2^maxm-amplitude LDS
+// exchange buffer); maxm in [9, 13].
+hipError_t launch_tile_pass_rb(int dtype, bool adj, int maxm, const PassArgs& A, uint64_t n_tiles, int batch,
+                               hipStream_t s);
 hipError_t launch_gate1(int dtype, void* psi, int64_t bstride, int batch, int n, int t, uint64_t cmask,
                         const void* ctab, int64_t ctab_bstride, int mat, hipStream_t s);
 hipError_t launch_gate2(int dtype, void* psi, int64_t bstride, int batch, int n, int ta, int tb,

@@ -254,7 +254,7 @@ __global__ __launch_bounds__(NT) void tile_pass(PassArgs A) {
     } else if (on && type == OP_ZZ) {
       const int first = ld(&O->first), count = ld(&O->count), mat = ld(&O->mat), gen = ld(&O->gen);
       if (active) {
-        const int32_t* ed = A.edges + 2 * first;
+        const ZZEdge* ed = A.edges + first;
         C v[RA], w[RA];
 #pragma unroll
         for (int k = 0; k < RA; ++k) {
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(NT) void tile_pass(PassArgs A) {
 #pragma unroll
         for (int k = 0; k < RA; ++k) cnt[k] = 0;
         for (int e = 0; e < count; ++e) {
-          const int u = ld(ed + 2 * e), vv = ld(ed + 2 * e + 1);
+          const int u = ld(&ed[e].u), vv = ld(&ed[e].v);
 #pragma unroll
           for (int k = 0; k < RA; ++k) cnt[k] += (int)(((xk[k] >> u) ^ (xk[k] >> vv)) & 1);
         }
@@ -304,6 +304,298 @@ __global__ __launch_bounds__(NT) void tile_pass(PassArgs A) {
         psi[xk[k]] = sp[j];
         if (ADJ) lam[xk[k]] = sl[j];
       }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Register-blocked tile pass.  Each of the 2^(m-RB) threads keeps 2^RB amplitudes of the
+// tile in registers.  The local bits in the current register mask are "register bits":
+// a gate on them is pure VALU work inside one thread.  A REMAP op changes which local bits
+// are register bits by one write and one read of the tile through LDS (XOR-swizzled so
+// every access pattern spreads over the banks).  Gates on other bits are never issued:
+// the planner groups each pass's gates into register rounds.
+// ------------------------------------------------------------------------------------------
+template <int S>  // S = log2(amplitudes per 128-byte LDS row)
+__device__ __forceinline__ int swz(int j) {
+  int f = 0;
+#pragma unroll
+  for (int sh = S; sh < 16; sh += S) f ^= j >> sh;
+  return j ^ (f & ((1 << S) - 1));
+}
+
+template <int I, int NR, bool ADJ, typename C>
+__device__ __forceinline__ void reg1(C* v, C* w, const int* jk, uint32_t lm, const C* U, bool grad,
+                                     const C* G, double& acc) {
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    if (k & (1 << I)) continue;
+    const int k1 = k | (1 << I);
+    if (((uint32_t)jk[k] & lm) != lm) continue;
+    const C a0 = v[k], a1 = v[k1];
+    if (ADJ) {
+      const C b0 = w[k], b1 = w[k1];
+      if (grad) acc += im_conj_mul(b0, cdot2(G[0], a0, G[1], a1)) + im_conj_mul(b1, cdot2(G[2], a0, G[3], a1));
+      w[k] = cdot2(U[0], b0, U[1], b1);
+      w[k1] = cdot2(U[2], b0, U[3], b1);
+    }
+    v[k] = cdot2(U[0], a0, U[1], a1);
+    v[k1] = cdot2(U[2], a0, U[3], a1);
+  }
+}
+
+template <typename C>
+__device__ __forceinline__ void mat4(const C* M, const C* x, C* y) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    C o = cdot2(M[4 * r], x[0], M[4 * r + 1], x[1]);
+    y[r] = cdot2(C{1, 0}, o, M[4 * r + 2], x[2]);
+    y[r] = cdot2(C{1, 0}, y[r], M[4 * r + 3], x[3]);
+  }
+}
+
+template <int RB, bool ADJ, typename C>
+__device__ __forceinline__ void reg1_dispatch(int i, C* v, C* w, const int* jk, uint32_t lm, const C* U, bool grad,
+                                              const C* G, double& acc) {
+  constexpr int NR = 1 << RB;
+  switch (i) {
+    case 0: reg1<0, NR, ADJ>(v, w, jk, lm, U, grad, G, acc); break;
+    case 1: reg1<1, NR, ADJ>(v, w, jk, lm, U, grad, G, acc); break;
+    case 2: reg1<2, NR, ADJ>(v, w, jk, lm, U, grad, G, acc); break;
+    default:
+      if constexpr (RB > 3) reg1<(RB > 3 ? 3 : 0), NR, ADJ>(v, w, jk, lm, U, grad, G, acc);
+      break;
+  }
+}
+
+__device__ __forceinline__ int insert_zero(int t, int p) { return ((t >> p) << (p + 1)) | (t & ((1 << p) - 1)); }
+
+template <typename R, int RB, int MAXM, bool ADJ>
+__global__ __launch_bounds__(1 << (MAXM - RB)) void tile_pass_rb(PassArgs A) {
+  using C = typename CT<R>::T;
+  static_assert(RB == 3, "layouts are encoded with three register bits");
+  constexpr int NT = 1 << (MAXM - RB);
+  constexpr int NR = 1 << RB;
+  constexpr int S = sizeof(R) == 8 ? 3 : 4;
+  __shared__ C buf[1 << MAXM];
+  __shared__ double red[NT >= 64 ? NT / 64 : 1];
+
+  const int tid = threadIdx.x;
+  const int m = A.m;
+  const int nloc = 1 << m;
+  const bool active = tid < (nloc >> RB);
+  const uint64_t tile = blockIdx.x;
+  const int b = blockIdx.y;
+  const uint64_t TM = A.tile_mask;
+  const uint64_t full = (A.n_qubits >= 64) ? ~0ull : ((1ull << A.n_qubits) - 1);
+  const uint64_t base = pdep64(tile, full & ~TM);
+
+  C* psi = reinterpret_cast<C*>(A.psi) + (int64_t)b * A.bstride;
+  C* lam = ADJ ? reinterpret_cast<C*>(A.lam) + (int64_t)b * A.bstride : nullptr;
+  const C* src = A.src ? reinterpret_cast<const C*>(A.src) + (int64_t)b * A.src_bstride : psi;
+  const C* T = reinterpret_cast<const C*>(A.ctab) + (int64_t)b * A.ctab_bstride;
+
+  // Local index of register slot k: the thread id with zeros inserted at the three
+  // register bits, plus k spread over them.
+  int jk[NR];
+  auto layout = [&](int lr, int* jo) {
+    const int p0 = __builtin_ctz(lr), p1 = __builtin_ctz(lr & (lr - 1)), p2 = 31 - __builtin_clz(lr);
+    const int jt = insert_zero(insert_zero(insert_zero(tid, p0), p1), p2);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) jo[k] = jt | ((k & 1) << p0) | (((k >> 1) & 1) << p1) | (((k >> 2) & 1) << p2);
+  };
+  // Global index of a local index: two lookup tables of deposits into the tile mask
+  // (local bits 0..6 and 7..13), built once per workgroup.
+  __shared__ uint64_t dep_lo[128], dep_hi[128];
+  if (tid < 128) {
+    dep_lo[tid] = pdep64((uint64_t)tid, TM);
+    dep_hi[tid] = pdep64((uint64_t)tid << 7, TM);
+  }
+  for (int i = tid + NT; i < 128; i += NT) {
+    dep_lo[i] = pdep64((uint64_t)i, TM);
+    dep_hi[i] = pdep64((uint64_t)i << 7, TM);
+  }
+  __syncthreads();
+  auto globals = [&](uint64_t* xo) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) xo[k] = base | dep_lo[jk[k] & 127] | dep_hi[jk[k] >> 7];
+  };
+  layout(A.lr0, jk);
+
+  C v[NR], w[NR];
+  if (active) {
+    uint64_t xk[NR];
+    globals(xk);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      v[k] = src[xk[k]];
+      if (ADJ) w[k] = lam[xk[k]];
+    }
+  }
+  // bit q of the global index of local index j
+  auto gbit = [&](int j, int l, int q) -> int { return l >= 0 ? (j >> l) & 1 : (int)((base >> q) & 1); };
+
+  double acc = 0.0;
+  for (int oi = 0; oi < A.n_ops; ++oi) {
+    const TileOp* O = A.ops + oi;
+    const int type = ld(&O->type);
+    const uint64_t omask = ld(&O->omask);
+    const bool on = (base & omask) == omask;
+    if (type == OP_REMAP) {
+      int jn[NR];
+      layout(ld(&O->a), jn);
+      if (active) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) buf[swz<S>(jk[k])] = v[k];
+      }
+      __syncthreads();
+      if (active) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) v[k] = buf[swz<S>(jn[k])];
+      }
+      if (ADJ) {
+        __syncthreads();
+        if (active) {
+#pragma unroll
+          for (int k = 0; k < NR; ++k) buf[swz<S>(jk[k])] = w[k];
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+          for (int k = 0; k < NR; ++k) w[k] = buf[swz<S>(jn[k])];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NR; ++k) jk[k] = jn[k];
+      __syncthreads();
+    } else if (on && active && type == OP_DENSE1) {
+      const int mat = ld(&O->mat), gen = ld(&O->gen);
+      C U[4], G[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) U[r] = ldc(T + mat + r);
+      const bool grad = ADJ && gen >= 0;
+      if (grad) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) G[r] = ldc(T + gen + r);
+      }
+      reg1_dispatch<RB, ADJ>(ld(&O->a), v, w, jk, ld(&O->lmask), U, grad, G, acc);
+    } else if (on && type == OP_DENSE2) {
+      // two-qubit dense gate on local bits a, b, applied to the tile staged in LDS (no
+      // gradient: parameterized two-qubit rotations are lowered to RZZ with basis changes)
+      const int a = ld(&O->a), bb = ld(&O->b), mat = ld(&O->mat);
+      const int lo = a < bb ? a : bb, hi = a < bb ? bb : a;
+      const uint32_t lm = ld(&O->lmask);
+      auto apply_staged = [&](C (&reg)[NR]) {
+        if (active) {
+#pragma unroll
+          for (int k = 0; k < NR; ++k) buf[swz<S>(jk[k])] = reg[k];
+        }
+        __syncthreads();
+        for (int p = tid; p < (nloc >> 2); p += NT) {
+          const int t = insert_zero(insert_zero(p, lo), hi);
+          if (((uint32_t)t & lm) != lm) continue;
+          const int idx[4] = {t, t | (1 << a), t | (1 << bb), t | (1 << a) | (1 << bb)};
+          C x[4], y[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) x[r] = buf[swz<S>(idx[r])];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            y[r] = cdot2(ldc(T + mat + 4 * r), x[0], ldc(T + mat + 4 * r + 1), x[1]);
+            y[r] = cdot2(C{1, 0}, y[r], ldc(T + mat + 4 * r + 2), x[2]);
+            y[r] = cdot2(C{1, 0}, y[r], ldc(T + mat + 4 * r + 3), x[3]);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) buf[swz<S>(idx[r])] = y[r];
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+          for (int k = 0; k < NR; ++k) reg[k] = buf[swz<S>(jk[k])];
+        }
+        __syncthreads();
+      };
+      apply_staged(v);
+      if (ADJ) apply_staged(w);
+    } else if (on && active && type == OP_DIAG) {
+      const int first = ld(&O->first), count = ld(&O->count);
+      C ph[NR];
+      int sign[NR];
+      double gw[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) { ph[k] = C{1, 0}; sign[k] = 0; gw[k] = 0.0; }
+      for (int e = 0; e < count; ++e) {
+        const DiagEntry* d = A.diag + first + e;
+        const uint64_t ocm = ld(&d->ocmask);
+        if ((base & ocm) != ocm) continue;  // an outside control is 0 in this tile
+        const uint32_t lcm = ld(&d->lcmask);
+        if (ld(&d->kind) == DIAG_SIGN) {
+#pragma unroll
+          for (int k = 0; k < NR; ++k) sign[k] ^= (int)(((uint32_t)jk[k] & lcm) == lcm);
+        } else {
+          const int l0 = ld(&d->l0), l1 = ld(&d->l1), q0 = ld(&d->q0), q1 = ld(&d->q1);
+          const int mat = ld(&d->mat);
+          const int dg = ADJ ? ld(&d->gen) : -1;
+#pragma unroll
+          for (int k = 0; k < NR; ++k) {
+            if (((uint32_t)jk[k] & lcm) != lcm) continue;
+            const int idx = gbit(jk[k], l0, q0) | (q1 >= 0 ? gbit(jk[k], l1, q1) << 1 : 0);
+            ph[k] = cmul(ph[k], ldc(T + mat + idx));
+            if (ADJ && dg >= 0) gw[k] += (double)ldc(T + dg + idx).x;
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        C p = ph[k];
+        if (sign[k]) { p.x = -p.x; p.y = -p.y; }
+        if (ADJ) {
+          acc += gw[k] * im_conj_mul(w[k], v[k]);
+          w[k] = cmul(w[k], p);
+        }
+        v[k] = cmul(v[k], p);
+      }
+    } else if (on && active && type == OP_ZZ) {
+      const int first = ld(&O->first), count = ld(&O->count), mat = ld(&O->mat), gen = ld(&O->gen);
+      const ZZEdge* ed = A.edges + first;
+      int cnt[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) cnt[k] = 0;
+      for (int e = 0; e < count; ++e) {
+        const int lu = ld(&ed[e].lu), lv = ld(&ed[e].lv), u = ld(&ed[e].u), vv = ld(&ed[e].v);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) cnt[k] += gbit(jk[k], lu, u) ^ gbit(jk[k], lv, vv);
+      }
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const C p = ldc(T + mat + cnt[k]);
+        if (ADJ) {
+          if (gen >= 0) acc += (double)ldc(T + gen + cnt[k]).x * im_conj_mul(w[k], v[k]);
+          w[k] = cmul(w[k], p);
+        }
+        v[k] = cmul(v[k], p);
+      }
+    }
+    if (ADJ && ld(&O->flush)) {
+      const double sv = wave_sum(acc);
+      if ((tid & 63) == 0) red[tid >> 6] = sv;
+      __syncthreads();
+      if (tid == 0) {
+        double s = 0.0;
+        for (int q = 0; q < (NT >= 64 ? NT / 64 : 1); ++q) s += red[q];
+        A.partials[((int64_t)b * A.n_pslots + ld(&O->pslot)) * (int64_t)gridDim.x + (int64_t)tile] = s;
+      }
+      acc = 0.0;
+      __syncthreads();
+    }
+  }
+
+  if (active) {
+    uint64_t xk[NR];
+    globals(xk);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      psi[xk[k]] = v[k];
+      if (ADJ) lam[xk[k]] = w[k];
     }
   }
 }
@@ -530,6 +822,38 @@ static hipError_t tile_dispatch(int maxm, const PassArgs& A, uint64_t n_tiles, i
     case 14: return tile_launch_one<R, 1024, 14, ADJ>(A, grid, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <typename R, int MAXM, bool ADJ>
+static hipError_t rb_launch_one(const PassArgs& A, dim3 grid, hipStream_t s) {
+  constexpr size_t bytes = (size_t)(2 * sizeof(R)) * ((size_t)1 << MAXM);
+  if constexpr (bytes <= 131072) {
+    tile_pass_rb<R, 3, MAXM, ADJ><<<grid, 1 << (MAXM - 3), 0, s>>>(A);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <typename R, bool ADJ>
+static hipError_t rb_dispatch(int maxm, const PassArgs& A, uint64_t n_tiles, int batch, hipStream_t s) {
+  const dim3 grid((unsigned)n_tiles, (unsigned)batch);
+  switch (maxm) {
+    case 9:  return rb_launch_one<R, 9, ADJ>(A, grid, s);
+    case 10: return rb_launch_one<R, 10, ADJ>(A, grid, s);
+    case 11: return rb_launch_one<R, 11, ADJ>(A, grid, s);
+    case 12: return rb_launch_one<R, 12, ADJ>(A, grid, s);
+    case 13: return rb_launch_one<R, 13, ADJ>(A, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_tile_pass_rb(int dtype, bool adj, int maxm, const PassArgs& A, uint64_t n_tiles, int batch,
+                               hipStream_t s) {
+  if (dtype == 0) return adj ? rb_dispatch<float, true>(maxm, A, n_tiles, batch, s)
+                             : rb_dispatch<float, false>(maxm, A, n_tiles, batch, s);
+  return adj ? rb_dispatch<double, true>(maxm, A, n_tiles, batch, s)
+             : rb_dispatch<double, false>(maxm, A, n_tiles, batch, s);
 }
 
 hipError_t launch_tile_pass(int dtype, bool adj, int maxm, const PassArgs& A, uint64_t n_tiles,

@@ -17,7 +17,13 @@ enum OpType : int32_t {
   OP_ZZ = 3,      // exp(-i theta/2 * sum_e Z_u Z_v) over EdgeTable[first .. first+count):
                   // amplitude x is multiplied by ctab[mat + c(x)], c(x) = #edges with
                   // x_u != x_v
+  OP_REMAP = 4,   // register-blocked passes: move amplitudes through LDS so that the
+                  // local bits in mask `a` become the register bits; `b` packs their
+                  // positions in ascending order (p0 | p1 << 8 | p2 << 16)
 };
+// In register-blocked passes each thread holds 2^RB amplitudes; DENSE1/DENSE2 then name
+// register-bit indices (a, b in [0, RB)) instead of local bits, and the other ops are
+// elementwise.  The initial (load) layout is PassArgs::lr0.
 
 // Matrices, phases and generator weights live in a per-batch-item table of complex
 // numbers (ctab); ops refer to it by offset.
@@ -47,7 +53,19 @@ struct DiagEntry {
   int32_t  mat;
   uint64_t cmask;      // PHASE: controls; SIGN: all bits that must be 1
   int32_t  gen;        // adjoint: ctab offset of 4 real generator weights (.x), or -1
-  int32_t  pad;
+  // The same entry relative to its pass's tile (used by register-blocked passes, which
+  // index amplitudes by tile-local position): l0 / l1 are the local bits of q0 / q1 (-1
+  // when the qubit lies outside the tile, whose bit then comes from the tile's base);
+  // lcmask / ocmask split cmask into local bits and outside (global) bits.
+  int32_t  l0, l1;
+  uint32_t lcmask;
+  uint64_t ocmask;
+};
+
+// One edge of an OP_ZZ run: global qubits (u, v) and their local bits in the pass's tile
+// (lu, lv; -1 when outside the tile).
+struct ZZEdge {
+  int32_t u, v, lu, lv;
 };
 
 struct PassArgs {
@@ -58,7 +76,7 @@ struct PassArgs {
   int64_t      src_bstride;
   const TileOp*    ops;
   const DiagEntry* diag;
-  const int32_t*   edges;     // (u, v) pairs of global qubits
+  const ZZEdge*    edges;
   const void*  ctab;          // per batch item: ctab + b * ctab_bstride complex entries
   int64_t      ctab_bstride;
   double*      partials;      // adjoint: [batch][n_pslots][n_tiles]
@@ -67,6 +85,8 @@ struct PassArgs {
   int32_t      n_qubits;
   int32_t      m;             // tile qubits = popcount(tile_mask)
   int32_t      n_pslots;
+  int32_t      lr0;           // register-blocked passes: local register mask at load time
+  int32_t      pad0;
 };
 
 // Pauli-sum pass over one group of terms sharing an x-mask.

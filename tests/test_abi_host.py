@@ -58,13 +58,22 @@ def test_plan_debug_rejects_invalid_circuits(bad):
     assert e.value.status == L.QSV_EINVAL
 
 
+def test_pauli_pair_rotations_lower_to_five_primitives():
+    L = _lib()
+    circ = W.circuit(4, [W.gate("RXX", (0, 3), params=(W.fixed_angle(0.3),)),
+                         W.gate("RYY", (1, 2), ctrls=(0,), params=(W.fixed_angle(0.2),))])
+    order, _, _, _ = L.qsv_plan_debug(circ, 4)
+    assert sorted(order.tolist()) == [0] * 5 + [1] * 5
+
+
 @pytest.mark.parametrize("n,m,seed", [(6, 3, 1), (8, 4, 2), (10, 5, 3), (12, 6, 4), (9, 9, 5)])
 def test_planned_order_is_equivalent(n, m, seed):
     """Every gate appears once, every pass's non-diagonal targets lie in its tile, and the
     planned execution order gives the same state as the original (oracle on the CPU)."""
     from oracle import statevector as O
     L = _lib()
-    circ = W.random_circuit(n, 120, seed, max_ctrls=2)
+    kinds = [k for k in W.GATE_KINDS if k not in ("RXX", "RYY")]  # one primitive per gate
+    circ = W.random_circuit(n, 120, seed, kinds=kinds, max_ctrls=2)
     order, pass_of, n_passes, masks = L.qsv_plan_debug(circ, m)
     assert sorted(order.tolist()) == list(range(len(circ["gates"])))
     assert np.all(np.diff(pass_of) >= 0) and n_passes == pass_of.max() + 1

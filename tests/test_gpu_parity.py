@@ -46,7 +46,7 @@ def _new_state(Q, n, dtype, psi0=None, tile=None, adj_tile=None):
 @pytest.mark.parametrize("n,tile,seed", [
     (1, None, 1), (2, None, 2), (3, None, 3), (5, None, 4), (8, None, 5), (12, None, 6),
     (14, None, 7), (16, None, 8), (17, 4, 9), (15, 6, 10), (13, 3, 11), (18, 0, 12), (11, 0, 13),
-    (19, None, 14),
+    (19, None, 14), (20, 9, 15), (18, 10, 16), (17, 11, 17), (16, 13, 18),
 ])
 def test_apply_circuit_matches_oracle(Q, dtype, n, tile, seed):
     """Random circuits over every gate kind, target position (0 and n-1 included) and up to
@@ -127,7 +127,7 @@ GRAD_KINDS = ["RX", "RY", "RZ", "PS", "RXX", "RYY", "RZZ", "U3", "H", "S", "T", 
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("n,adj_tile,ctrls,seed", [
     (2, None, 1, 1), (4, None, 2, 2), (7, None, 2, 3), (10, None, 2, 4), (13, None, 2, 5),
-    (15, 4, 2, 6), (16, 6, 1, 7), (14, 3, 0, 8),
+    (15, 4, 2, 6), (16, 6, 1, 7), (14, 3, 0, 8), (16, 9, 2, 9), (17, 11, 1, 10), (18, 10, 0, 11),
 ])
 def test_adjoint_gradient_matches_oracle(Q, dtype, n, adj_tile, ctrls, seed):
     """Every parameterized kind (U3 included), shared parameters, controlled rotations."""
