@@ -188,6 +188,20 @@ int qsv_expectation_and_grad_batch(qsv_state* s, const qsv_circuit* c, const qsv
                                    const double* params, size_t batch, size_t n_params,
                                    double* out_E, double* out_grad);
 
+/* Differentiable evaluation in two halves (the forward and backward of an autograd
+ * function).  qsv_forward_batch computes out_E[b] like qsv_expectation_batch and keeps the
+ * evolved states in the state's workspace.  qsv_backward_batch then runs lambda = H psi and
+ * the adjoint reverse sweep over those states, holding only psi and lambda per batch item,
+ * and returns out_grad[b][p] = dE_weights[b] * dE_b / dparams[b][p] (a vector-Jacobian
+ * product).  If the kept states do not match the call (different circuit, Hamiltonian,
+ * parameters or batch, or another call used the workspace in between) the forward sweep
+ * is recomputed first, so the result never depends on call order. */
+int qsv_forward_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h,
+                      const double* params, size_t batch, size_t n_params, double* out_E);
+int qsv_backward_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h,
+                       const double* params, size_t batch, size_t n_params,
+                       const double* dE_weights, double* out_grad);
+
 /* Energies only, for a batch of parameter sets: out_E[batch] (no gradient). */
 int qsv_expectation_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h,
                           const double* params, size_t batch, size_t n_params, double* out_E);

@@ -34,6 +34,7 @@ EXPORTED = (
     "qsv_apply_circuit", "qsv_expectation", "qsv_apply_pauli_sum",
     "qsv_expectation_and_grad", "qsv_expectation_and_grad_batch", "qsv_expectation_batch",
     "qsv_param_shift_grad_batch", "qsv_plan_debug", "qsv_profile_read",
+    "qsv_forward_batch", "qsv_backward_batch",
 )
 
 
@@ -117,6 +118,10 @@ def lib():
             "qsv_param_shift_grad_batch": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), dp, sz, sz,
                                             dp, dp], C.c_int),
             "qsv_profile_read": ([vp, i32, dp, C.POINTER(i64), dp], C.c_int),
+            "qsv_forward_batch": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), dp, sz, sz, dp],
+                                  C.c_int),
+            "qsv_backward_batch": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), dp, sz, sz, dp, dp],
+                                   C.c_int),
             "qsv_plan_debug": ([C.POINTER(qsv_circuit), i32, C.POINTER(i32), C.POINTER(i32), i32, C.POINTER(i32),
                                 C.POINTER(i32), C.POINTER(C.c_uint64), i32], C.c_int),
         }
@@ -358,6 +363,23 @@ def qsv_expectation_batch(s, circuit, hamiltonian, params):
     E = np.zeros(B)
     check(lib().qsv_expectation_batch(s.handle, c.ptr, h.ptr, _dp(p), B, P, _dp(E)))
     return E
+
+
+def qsv_forward_batch(s, circuit, hamiltonian, params):
+    c, h = _circuit(circuit), _pauli(hamiltonian)
+    p, B, P = _batch_params(params)
+    E = np.zeros(B)
+    check(lib().qsv_forward_batch(s.handle, c.ptr, h.ptr, _dp(p), B, P, _dp(E)))
+    return E
+
+
+def qsv_backward_batch(s, circuit, hamiltonian, params, dE_weights):
+    c, h = _circuit(circuit), _pauli(hamiltonian)
+    p, B, P = _batch_params(params)
+    w = np.ascontiguousarray(np.broadcast_to(np.asarray(dE_weights, dtype=np.float64), (B,)))
+    g = np.zeros((B, P))
+    check(lib().qsv_backward_batch(s.handle, c.ptr, h.ptr, _dp(p), B, P, _dp(w), _dp(g)))
+    return g
 
 
 def qsv_param_shift_grad_batch(s, circuit, hamiltonian, params):

@@ -72,6 +72,8 @@ struct qsv_state {
   size_t stage_bytes = 0;
   hipEvent_t stage_ev = nullptr;
   bool stage_pending = false;
+  // identity of the evolved states left in ws_psi by qsv_forward_batch ("" if none)
+  std::string fwd_token;
   std::unordered_map<std::string, std::unique_ptr<Plan>> plans;
 
   size_t amp_bytes() const { return dtype == QSV_C64 ? 8 : 16; }
@@ -400,19 +402,27 @@ qsv_state* check_state(const qsv_state* s) {
 
 // Energies (and optionally gradients) of `batch` bound tables.  Shared by the batch entry
 // points and the parameter-shift comparator.
+// run_fwd = false: the evolved states of an earlier forward-only call are still in the
+// workspace (qsv_backward_batch), so only lambda and the reverse sweep run.
 void energies_and_grads(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h, const Plan& fwd,
                         const std::vector<cplx>& ctab_fwd, const Plan* adj, const std::vector<cplx>* ctab_adj,
-                        int batch, double* out_E, std::vector<double>* gcols) {
+                        int batch, double* out_E, std::vector<double>* gcols, bool run_fwd = true) {
   const uint64_t N = s->namps();
   const int64_t bstride = (int64_t)N;
+  s->fwd_token.clear();
   s->ws_psi.reserve((size_t)batch * N * s->amp_bytes());
   if (adj) s->ws_lam.reserve((size_t)batch * N * s->amp_bytes());
   Uploaded up[2];
-  UploadReq req[2] = {{&fwd, &ctab_fwd, batch}, {adj, ctab_adj, batch}};
-  upload_plans(s, req, adj ? 2 : 1, up);
+  if (run_fwd) {
+    UploadReq req[2] = {{&fwd, &ctab_fwd, batch}, {adj, ctab_adj, batch}};
+    upload_plans(s, req, adj ? 2 : 1, up);
+  } else {
+    UploadReq req = {adj, ctab_adj, batch};
+    upload_plans(s, &req, 1, &up[1]);
+  }
   DevPauli dp = upload_pauli(s, h, s->pauli);
   const int G = (int)dp.groups.size();
-  run_forward(s, fwd, up[0], s->ws_psi.p, bstride, s->psi, 0, batch);
+  if (run_fwd) run_forward(s, fwd, up[0], s->ws_psi.p, bstride, s->psi, 0, batch);
   // output columns: energies [batch][2G] then gradient slots [batch][P]
   const int P = adj ? adj->n_pslots : 0;
   const size_t ne = (size_t)batch * 2 * G, ng = (size_t)batch * P;
@@ -746,6 +756,67 @@ int qsv_expectation_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_su
     for (size_t b = 0; b < batch; ++b)
       bind_ctab(fwd, c, params + b * n_params, nullptr, 0, cf.data() + b * fwd.ctab_size);
     energies_and_grads(s, c, h, fwd, cf, nullptr, nullptr, (int)batch, out_E, nullptr);
+  });
+}
+
+static std::string forward_token(const qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h,
+                                 const double* params, size_t batch, size_t n_params) {
+  std::string t = structure_key(c, false, plan_options(s, false, true));
+  auto put = [&](const void* p, size_t n) { if (n) t.append(reinterpret_cast<const char*>(p), n); };
+  for (size_t i = 0; i < c->n_gates; ++i) {
+    put(c->gates[i].param_coeff, sizeof(double) * 3);
+    put(c->gates[i].angle_const, sizeof(double) * 3);
+    put(&c->gates[i].matrix_offset, sizeof(int64_t));
+  }
+  if (c->matrices) put(c->matrices, c->n_matrix_doubles * sizeof(double));
+  put(h->coeffs, h->n_terms * sizeof(double));
+  put(h->x_masks, h->n_terms * sizeof(uint64_t));
+  put(h->z_masks, h->n_terms * sizeof(uint64_t));
+  put(params, batch * n_params * sizeof(double));
+  put(&batch, sizeof(batch));
+  put(&s->psi, sizeof(void*));
+  return t;
+}
+
+int qsv_forward_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h, const double* params, size_t batch,
+                      size_t n_params, double* out_E) {
+  return guarded([&] {
+    batch_common(s, c, h, params, batch, n_params, out_E);
+    const Plan& fwd = get_plan(s, c, false, true);
+    std::vector<cplx> cf((size_t)batch * fwd.ctab_size);
+    for (size_t b = 0; b < batch; ++b)
+      bind_ctab(fwd, c, params + b * n_params, nullptr, 0, cf.data() + b * fwd.ctab_size);
+    energies_and_grads(s, c, h, fwd, cf, nullptr, nullptr, (int)batch, out_E, nullptr);
+    s->fwd_token = forward_token(s, c, h, params, batch, n_params);
+  });
+}
+
+int qsv_backward_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h, const double* params,
+                       size_t batch, size_t n_params, const double* dE_weights, double* out_grad) {
+  return guarded([&] {
+    std::vector<double> E(batch > 0 && batch <= 65535 ? batch : 1);
+    batch_common(s, c, h, params, batch, n_params, E.data());
+    if (n_params && !out_grad) fail(QSV_EINVAL, "out_grad is NULL");
+    if (!dE_weights) fail(QSV_EINVAL, "dE_weights is NULL");
+    for (size_t b = 0; b < batch; ++b)
+      if (!std::isfinite(dE_weights[b])) fail(QSV_EINVAL, "non-finite dE weight");
+    const Plan& fwd = get_plan(s, c, false, true);
+    const Plan& adj = get_plan(s, c, true, true);
+    const bool kept = !s->fwd_token.empty() && s->fwd_token == forward_token(s, c, h, params, batch, n_params);
+    std::vector<cplx> cf(kept ? 0 : (size_t)batch * fwd.ctab_size), ca((size_t)batch * adj.ctab_size);
+    for (size_t b = 0; b < batch; ++b) {
+      if (!kept) bind_ctab(fwd, c, params + b * n_params, nullptr, 0, cf.data() + b * fwd.ctab_size);
+      bind_ctab(adj, c, params + b * n_params, nullptr, 0, ca.data() + b * adj.ctab_size);
+    }
+    std::vector<double> gcols;
+    energies_and_grads(s, c, h, fwd, cf, &adj, &ca, (int)batch, E.data(), &gcols, !kept);
+    const int P = adj.n_pslots;
+    for (size_t b = 0; b < batch; ++b) {
+      double* g = out_grad + b * n_params;
+      for (size_t k = 0; k < n_params; ++k) g[k] = 0.0;
+      for (int k = 0; k < P; ++k) g[adj.pslot_param[k]] += gcols[b * P + k];
+      for (size_t k = 0; k < n_params; ++k) g[k] *= dE_weights[b];
+    }
   });
 }
 

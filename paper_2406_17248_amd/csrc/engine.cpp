@@ -626,9 +626,55 @@ struct PassEmitter {
     op.pslot = -1;
     push(op, -1);
   }
+  // Diagonal primitives are buffered and emitted as late as possible: a dense primitive
+  // commutes with every buffered diagonal one that does not touch its non-diagonal
+  // qubits, so the buffer is flushed (as few merged DIAG / ZZ ops) only when a dense
+  // primitive needs it, or at the end of the pass.
+  std::vector<int32_t> pending;
+  uint64_t pending_touched = 0;
+
   // Emit ops for primitives seq (in order).  reg_index: for register-blocked passes the
   // register index of each local bit (-1 if not a register bit), else nullptr.
   void emit(const std::vector<int32_t>& seq, const int* reg_index) {
+    for (int32_t pi : seq) {
+      const Prim& p = plan.prims[pi];
+      if (!(p.type == P_DENSE1 || p.type == P_DENSE2)) {
+        pending.push_back(pi);
+        pending_touched |= p.touched;
+        continue;
+      }
+      if (pending_touched & p.nondiag) flush();
+      TileOp op{};
+      op.gen = -1;
+      op.pslot = -1;
+      op.flush = 0;
+      op.type = p.type == P_DENSE1 ? OP_DENSE1 : OP_DENSE2;
+      if (p.type == P_DENSE1 && reg_index) {
+        op.a = reg_index[loc[p.q0]];
+        if (op.a < 0) fail(QSV_EINVAL, "internal: dense target is not a register bit");
+      } else {
+        op.a = loc[p.q0];
+        op.b = p.type == P_DENSE2 ? loc[p.q1] : 0;
+      }
+      op.lmask = local_mask(p.cmask & T);
+      op.omask = p.cmask & ~T;
+      op.mat = alloc(prim_size(p));
+      plan.fills.push_back({F_PRIM_MATRIX, pi, 0, op.mat});
+      int32_t prm = -1;
+      if (adjoint && p.gen != G_NONE) {
+        if (reg_index && p.type == P_DENSE2) fail(QSV_EINVAL, "internal: gradient on an LDS two-qubit op");
+        op.gen = alloc(prim_size(p));
+        plan.fills.push_back({F_PRIM_GEN, pi, 0, op.gen});
+        prm = p.param;
+      }
+      push(op, prm);
+    }
+  }
+
+  void flush() {
+    const std::vector<int32_t> seq = pending;
+    pending.clear();
+    pending_touched = 0;
     size_t k = 0;
     while (k < seq.size()) {
       const Prim& p = plan.prims[seq[k]];
@@ -636,30 +682,6 @@ struct PassEmitter {
       op.gen = -1;
       op.pslot = -1;
       op.flush = 0;
-      if (p.type == P_DENSE1 || p.type == P_DENSE2) {
-        op.type = p.type == P_DENSE1 ? OP_DENSE1 : OP_DENSE2;
-        if (p.type == P_DENSE1 && reg_index) {
-          op.a = reg_index[loc[p.q0]];
-          if (op.a < 0) fail(QSV_EINVAL, "internal: dense target is not a register bit");
-        } else {
-          op.a = loc[p.q0];
-          op.b = p.type == P_DENSE2 ? loc[p.q1] : 0;
-        }
-        op.lmask = local_mask(p.cmask & T);
-        op.omask = p.cmask & ~T;
-        op.mat = alloc(prim_size(p));
-        plan.fills.push_back({F_PRIM_MATRIX, seq[k], 0, op.mat});
-        int32_t prm = -1;
-        if (adjoint && p.gen != G_NONE) {
-          if (reg_index && p.type == P_DENSE2) fail(QSV_EINVAL, "internal: gradient on an LDS two-qubit op");
-          op.gen = alloc(prim_size(p));
-          plan.fills.push_back({F_PRIM_GEN, seq[k], 0, op.gen});
-          prm = p.param;
-        }
-        push(op, prm);
-        ++k;
-        continue;
-      }
       if (opt.fuse_zz && zz_fusable(p, c)) {
         size_t e = k + 1;
         while (e < seq.size() && zz_fusable(plan.prims[seq[e]], c) &&
@@ -687,11 +709,11 @@ struct PassEmitter {
       }
       op.type = OP_DIAG;
       op.first = (int32_t)plan.diag.size();
+      op.b = 0;  // 1 when the run has a phase entry (else only sign flips)
       int32_t run_param = -1;
       size_t e = k;
       while (e < seq.size()) {
         const Prim& q = plan.prims[seq[e]];
-        if (!(q.type == P_DIAG1 || q.type == P_DIAG2 || q.type == P_SIGN)) break;
         if (e > k && opt.fuse_zz && zz_fusable(q, c) && e + 1 < seq.size() &&
             zz_fusable(plan.prims[seq[e + 1]], c) &&
             same_binding(c->gates[plan.prims[seq[e + 1]].gate], c->gates[q.gate]))
@@ -713,6 +735,7 @@ struct PassEmitter {
         d.mat = -1;
         d.gen = -1;
         if (q.type != P_SIGN) {
+          op.b = 1;
           d.mat = alloc(prim_size(q));
           plan.fills.push_back({F_PRIM_MATRIX, seq[e], 0, d.mat});
         }
@@ -803,6 +826,7 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
     }
     if (!rb) {
       em.emit(ps.prims, nullptr);
+      em.flush();
     } else {
       const int r = kRegBits;
       const std::vector<Pass> rounds = plan_rounds(plan.prims, ps.prims, ps.tile_mask, r);
@@ -826,6 +850,7 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
         em.emit(rounds[ri].prims, reg_index);
       }
       if (cur < 0) dp.lr0 = cur = top;
+      em.flush();
       if (cur & low_mask) em.remap(top);
     }
     // gradient slots: consecutive ops of one parameter share an accumulator

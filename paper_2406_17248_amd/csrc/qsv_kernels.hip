@@ -516,6 +516,27 @@ __global__ __launch_bounds__(1 << (MAXM - RB)) void tile_pass_rb(PassArgs A) {
       };
       apply_staged(v);
       if (ADJ) apply_staged(w);
+    } else if (on && active && type == OP_DIAG && !ld(&O->b)) {
+      // sign flips only (Z, CZ, multi-controlled Z): parity of the satisfied masks
+      const int first = ld(&O->first), count = ld(&O->count);
+      int sign[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) sign[k] = 0;
+      for (int e = 0; e < count; ++e) {
+        const DiagEntry* d = A.diag + first + e;
+        const uint64_t ocm = ld(&d->ocmask);
+        if ((base & ocm) != ocm) continue;
+        const uint32_t lcm = ld(&d->lcmask);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) sign[k] ^= (int)(((uint32_t)jk[k] & lcm) == lcm);
+      }
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        if (sign[k]) {
+          v[k].x = -v[k].x; v[k].y = -v[k].y;
+          if (ADJ) { w[k].x = -w[k].x; w[k].y = -w[k].y; }
+        }
+      }
     } else if (on && active && type == OP_DIAG) {
       const int first = ld(&O->first), count = ld(&O->count);
       C ph[NR];
