@@ -213,6 +213,30 @@ int qsv_param_shift_grad_batch(qsv_state* s, const qsv_circuit* c, const qsv_pau
                                const double* params, size_t batch, size_t n_params,
                                double* out_E, double* out_grad);
 
+/* ---- batches of uneven circuits --------------------------------------------------------
+ * Many independent circuits, each with its own Pauli-sum Hamiltonian and parameters
+ * (section 4.1's batch mode, with circuits of different sizes and depths), evaluated
+ * together from |0...0>: pass round r of every circuit runs in one launch, lambda = H psi of
+ * every circuit in one gather-form launch, and the whole evaluation is captured once into
+ * a HIP graph that each call replays.  Circuits have 1..28 qubits.  The library copies the
+ * circuits and Hamiltonians at creation.  Circuit i's parameters are params[off[i] ..
+ * off[i+1]) with off from qsv_batch_info (n_params of a circuit = largest param_index + 1). */
+typedef struct qsv_batch qsv_batch;
+int qsv_batch_create(int32_t dtype, size_t n_circuits, const qsv_circuit* circuits,
+                     const qsv_pauli_sum* hams, qsv_batch** out);
+int qsv_batch_destroy(qsv_batch* b);
+/* total parameter count, offsets (n_circuits + 1 entries, or NULL), device time of the last
+ * graph replay in ms, current tile width; any pointer may be NULL. */
+int qsv_batch_info(const qsv_batch* b, size_t* total_params, int64_t* param_offsets, double* last_ms,
+                   int32_t* tile_qubits);
+/* Fix the tile (fusion) width of every fused pass, in [9, 13]; rebuilds plans and graph. */
+int qsv_batch_set_tile(qsv_batch* b, int32_t tile_qubits);
+/* Autotuner: time the whole evaluation at each candidate tile width (10..13) with these
+ * parameters on the device, keep the fastest, return it in *out_tile. */
+int qsv_batch_autotune(qsv_batch* b, const double* params, int32_t* out_tile);
+/* out_E[i] = <H_i> of circuit i; out_grad (may be NULL) has the layout of params. */
+int qsv_batch_expectation_and_grad(qsv_batch* b, const double* params, double* out_E, double* out_grad);
+
 /* ---- profiling ----------------------------------------------------------------------- */
 /* Kernel classes timed when QSV_OPT_PROFILE is 1. */
 enum qsv_kernel_class {

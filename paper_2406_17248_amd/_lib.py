@@ -35,6 +35,8 @@ EXPORTED = (
     "qsv_expectation_and_grad", "qsv_expectation_and_grad_batch", "qsv_expectation_batch",
     "qsv_param_shift_grad_batch", "qsv_plan_debug", "qsv_profile_read",
     "qsv_forward_batch", "qsv_backward_batch",
+    "qsv_batch_create", "qsv_batch_destroy", "qsv_batch_info", "qsv_batch_set_tile", "qsv_batch_autotune",
+    "qsv_batch_expectation_and_grad",
 )
 
 
@@ -118,6 +120,13 @@ def lib():
             "qsv_param_shift_grad_batch": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), dp, sz, sz,
                                             dp, dp], C.c_int),
             "qsv_profile_read": ([vp, i32, dp, C.POINTER(i64), dp], C.c_int),
+            "qsv_batch_create": ([i32, sz, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), C.POINTER(vp)],
+                                 C.c_int),
+            "qsv_batch_destroy": ([vp], C.c_int),
+            "qsv_batch_info": ([vp, C.POINTER(sz), C.POINTER(i64), dp, C.POINTER(i32)], C.c_int),
+            "qsv_batch_set_tile": ([vp, i32], C.c_int),
+            "qsv_batch_autotune": ([vp, dp, C.POINTER(i32)], C.c_int),
+            "qsv_batch_expectation_and_grad": ([vp, dp, dp, dp], C.c_int),
             "qsv_forward_batch": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), dp, sz, sz, dp],
                                   C.c_int),
             "qsv_backward_batch": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), dp, sz, sz, dp, dp],
@@ -411,3 +420,64 @@ def qsv_plan_debug(circuit, tile_qubits):
     k = n_entries.value
     return (np.array(order[:k]), np.array(pass_of[:k]), int(n_passes.value),
             np.array(masks[:n_passes.value], dtype=np.uint64))
+
+
+# ------------------------------------------------------------------------------------------
+# Batches of uneven circuits
+# ------------------------------------------------------------------------------------------
+class Batch:
+    """Many independent circuits with their own Hamiltonians (qsv_batch*)."""
+
+    def __init__(self, circuits, hamiltonians, dtype="c64"):
+        self._circs = [_circuit(c) for c in circuits]
+        self._hams = [_pauli(h) for h in hamiltonians]
+        carr = (qsv_circuit * len(self._circs))(*[c.c for c in self._circs])
+        harr = (qsv_pauli_sum * len(self._hams))(*[h.h for h in self._hams])
+        h = C.c_void_p()
+        check(lib().qsv_batch_create(_dt(dtype), len(self._circs), carr, harr, C.byref(h)))
+        self.handle = h
+        self.n = len(self._circs)
+        total = C.c_size_t()
+        offs = (C.c_int64 * (self.n + 1))()
+        check(lib().qsv_batch_info(self.handle, C.byref(total), offs, None, None))
+        self.total_params = total.value
+        self.offsets = np.array(offs[:], dtype=np.int64)
+
+    def __del__(self):
+        try:
+            if self.handle and _lib is not None:
+                _lib.qsv_batch_destroy(self.handle)
+                self.handle = C.c_void_p(None)
+        except Exception:
+            pass
+
+    def info(self):
+        ms, tile = C.c_double(), C.c_int32()
+        check(lib().qsv_batch_info(self.handle, None, None, C.byref(ms), C.byref(tile)))
+        return {"last_ms": ms.value, "tile_qubits": tile.value}
+
+
+def qsv_batch_create(circuits, hamiltonians, dtype="c64"):
+    return Batch(circuits, hamiltonians, dtype)
+
+
+def qsv_batch_set_tile(b, tile_qubits):
+    check(lib().qsv_batch_set_tile(b.handle, int(tile_qubits)))
+
+
+def qsv_batch_autotune(b, params):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    t = C.c_int32()
+    check(lib().qsv_batch_autotune(b.handle, _dp(p), C.byref(t)))
+    return t.value
+
+
+def qsv_batch_expectation_and_grad(b, params):
+    """(E[n_circuits], grad with the layout of params)."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    if p.size != b.total_params:
+        raise ValueError(f"expected {b.total_params} parameters, got {p.size}")
+    E = np.zeros(b.n)
+    g = np.zeros(max(p.size, 1))
+    check(lib().qsv_batch_expectation_and_grad(b.handle, _dp(p), _dp(E), _dp(g)))
+    return E, g[:p.size]

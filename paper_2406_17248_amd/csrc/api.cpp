@@ -11,43 +11,21 @@
 
 #include "../../include/qsv.h"
 #include "engine.h"
+#include "hip_util.h"
 #include "qsv_kernels.h"
 
 using namespace qsv;
 
+namespace qsv {
+std::string& last_error() {
+  thread_local std::string msg;
+  return msg;
+}
+}  // namespace qsv
+
 namespace {
 
-thread_local std::string g_last_error;
-
 [[noreturn]] void fail(int status, const std::string& msg) { throw Error{status, msg}; }
-
-void hip_check(hipError_t e, const char* what) {
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    fail(e == hipErrorOutOfMemory ? QSV_ENOMEM : QSV_EHIP, std::string(what) + ": " + hipGetErrorString(e));
-  }
-}
-
-// Grow-only device buffer.
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  void reserve(size_t need) {
-    if (need <= bytes) return;
-    if (p) hip_check(hipFree(p), "hipFree");
-    p = nullptr;
-    bytes = 0;
-    hip_check(hipMalloc(&p, need), "hipMalloc workspace");
-    bytes = need;
-  }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-};
-
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace
 
@@ -161,7 +139,7 @@ PlanOptions plan_options(const qsv_state* s, bool adjoint, bool fuse_zz) {
   if (adjoint && s->dtype == QSV_C128) o.tile_qubits = std::min(o.tile_qubits, 12);
   // tiles below the register-blocked range use the LDS-sweep kernel, whose adjoint
   // variant stages psi and lambda together
-  if (rb_capacity_host(s->dtype, std::min<int>(o.tile_qubits, s->n)) < 0)
+  if (std::min<int>(o.tile_qubits, s->n) < o.rb_min || rb_capacity_host(s->dtype, std::min<int>(o.tile_qubits, s->n)) < 0)
     o.tile_qubits = std::min<int>(o.tile_qubits, adjoint ? (s->dtype == QSV_C64 ? 12 : 11) : 13);
   o.low_qubits = s->dtype == QSV_C64 ? 4 : 3;
   o.fuse_zz = fuse_zz;
@@ -241,6 +219,7 @@ void upload_plans(qsv_state* s, const UploadReq* reqs, int n_req, Uploaded* out)
 hipError_t launch_pass(const qsv_state* s, const DevPass& dp, PassArgs A, int batch, bool adj) {
   A.lr0 = dp.lr0;
   const uint64_t tiles = 1ull << (s->n - dp.m);
+  A.n_tiles = (int64_t)tiles;
   if (dp.rb) return launch_tile_pass_rb(s->dtype, adj, dp.maxm, A, tiles, batch, s->stream);
   return launch_tile_pass(s->dtype, adj, dp.maxm, A, tiles, batch, s->stream);
 }
@@ -378,23 +357,6 @@ void run_pauli(qsv_state* s, const DevPauli& dp, const void* psi, void* lam, int
             "reduce");
 }
 
-int guarded(const std::function<void()>& f) {
-  try {
-    f();
-    g_last_error.clear();
-    return QSV_OK;
-  } catch (const Error& e) {
-    g_last_error = e.msg;
-    return e.status;
-  } catch (const std::bad_alloc&) {
-    g_last_error = "host allocation failed";
-    return QSV_ENOMEM;
-  } catch (...) {
-    g_last_error = "unexpected internal error";
-    return QSV_EINVAL;
-  }
-}
-
 qsv_state* check_state(const qsv_state* s) {
   if (!s) fail(QSV_EINVAL, "state is NULL");
   return const_cast<qsv_state*>(s);
@@ -493,7 +455,7 @@ const char* qsv_status_string(int status) {
   }
 }
 
-const char* qsv_last_error(void) { return g_last_error.c_str(); }
+const char* qsv_last_error(void) { return last_error().c_str(); }
 
 const char* qsv_version(void) { return "qsv 0.1 (gfx950)"; }
 

@@ -472,6 +472,23 @@ std::vector<Pass> plan_passes(const std::vector<Prim>& prims, int32_t n, int32_t
       }
       T |= 1ull << best_q;
     }
+    // Also try the low qubits plus every contiguous window of the others (this suits
+    // circuits with nearest-neighbour structure, where the greedy choice scatters) and keep
+    // the tile that runs the most dense primitives.
+    {
+      int best = -1;
+      schedule(prims, rem, T, nullptr, nullptr, &best);
+      const int free = m - low;
+      for (int start = low; start + free <= n; ++start) {
+        const uint64_t W = ((1ull << low) - 1) | (((1ull << free) - 1) << start);
+        int dense = 0;
+        schedule(prims, rem, W, nullptr, nullptr, &dense);
+        if (dense > best) {
+          best = dense;
+          T = W;
+        }
+      }
+    }
     Pass ps;
     std::vector<int32_t> left;
     schedule(prims, rem, T, &ps.prims, &left, nullptr);
@@ -512,7 +529,7 @@ static bool zz_fusable(const Prim& p, const qsv_circuit* c) {
 }
 
 int rb_capacity_host(int dtype, int m) {
-  if (m < kRegBits + 6 || m > 13) return -1;
+  if (m < kRegBits + 1 || m > 13) return -1;
   const size_t amp = dtype == 0 ? 8 : 16;
   return amp * ((size_t)1 << m) <= 131072 ? m : -1;
 }
@@ -805,8 +822,8 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
   }
 
   const int m = std::min<int>(std::max(opt.tile_qubits, 2), n);
-  const bool rb = opt.use_rb && rb_capacity_host(opt.dtype, m) >= 0;
-  const int maxm = rb ? m : tile_capacity_host(opt.dtype, adjoint, m);
+  const bool rb = opt.use_rb && m >= opt.rb_min && rb_capacity_host(opt.dtype, m) >= 0;
+  const int maxm = rb ? std::max(m, kRegBits + 6) : tile_capacity_host(opt.dtype, adjoint, m);
   if (maxm < 0) fail(QSV_EINVAL, "tile width does not fit in LDS for this dtype");
   const std::vector<Pass> passes = plan_passes(plan.prims, n, m, opt.low_qubits);
   const int low_local = std::max(0, std::min(opt.low_qubits, m - 2));
@@ -882,8 +899,8 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
 std::string structure_key(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
   std::string key;
   auto put = [&](const void* p, size_t n) { key.append(reinterpret_cast<const char*>(p), n); };
-  const int32_t head[7] = {c->n_qubits, adjoint ? 1 : 0, opt.tile_qubits, opt.low_qubits, opt.fuse_zz ? 1 : 0,
-                           opt.dtype, opt.use_rb ? 1 : 0};
+  const int32_t head[8] = {c->n_qubits, adjoint ? 1 : 0, opt.tile_qubits, opt.low_qubits, opt.fuse_zz ? 1 : 0,
+                           opt.dtype, opt.use_rb ? 1 : 0, opt.rb_min};
   put(head, sizeof(head));
   for (size_t i = 0; i < c->n_gates; ++i) {
     const qsv_gate& g = c->gates[i];

@@ -112,7 +112,8 @@ struct PlanOptions {
   int32_t low_qubits = 3;     // always in the tile (coalescing)
   bool    fuse_zz = true;     // fuse runs of equally-bound RZZ into one phase-table op
   int32_t dtype = 1;
-  bool    use_rb = true;      // register-blocked kernel for tiles of 9..13 qubits
+  bool    use_rb = true;      // register-blocked kernel for tiles of rb_min..13 qubits
+  int32_t rb_min = 9;         // smallest register-blocked tile (smaller ones idle threads)
 };
 
 // Validate a circuit against n_params (and the state's n).  Throws Error.

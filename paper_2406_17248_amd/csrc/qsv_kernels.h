@@ -13,6 +13,16 @@ hipError_t launch_tile_pass(int dtype, bool adj, int maxm, const PassArgs& A, ui
 // exchange buffer); maxm in [9, 13].
 hipError_t launch_tile_pass_rb(int dtype, bool adj, int maxm, const PassArgs& A, uint64_t n_tiles, int batch,
                                hipStream_t s);
+// Multi-circuit variants (batched uneven circuits).
+constexpr int kPauliChunk = 4096;  // amplitudes per workgroup of the multi-circuit Pauli pass
+hipError_t launch_tile_pass_rb_multi(int dtype, bool adj, int maxm, const PassArgs* items, const uint32_t* prefix,
+                                     int n_items, uint32_t n_wg, hipStream_t s);
+hipError_t launch_pauli_apply_multi(int dtype, const PauliJob* jobs, const uint32_t* prefix, int n_jobs, uint32_t n_wg,
+                                    hipStream_t s);
+hipError_t launch_reduce_segments(const double* in, const int64_t* offs, const int32_t* lens, const int32_t* strides,
+                                  double* out, int ncols, hipStream_t s);
+hipError_t launch_set_zero_multi(int dtype, void* const* ptrs, const int32_t* nq, const uint32_t* prefix, int n_jobs,
+                                 uint32_t n_wg, hipStream_t s);
 hipError_t launch_gate1(int dtype, void* psi, int64_t bstride, int batch, int n, int t, uint64_t cmask,
                         const void* ctab, int64_t ctab_bstride, int mat, hipStream_t s);
 hipError_t launch_gate2(int dtype, void* psi, int64_t bstride, int batch, int n, int ta, int tb,

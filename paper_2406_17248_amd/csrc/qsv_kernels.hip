@@ -371,7 +371,7 @@ __device__ __forceinline__ void reg1_dispatch(int i, C* v, C* w, const int* jk, 
 __device__ __forceinline__ int insert_zero(int t, int p) { return ((t >> p) << (p + 1)) | (t & ((1 << p) - 1)); }
 
 template <typename R, int RB, int MAXM, bool ADJ>
-__global__ __launch_bounds__(1 << (MAXM - RB)) void tile_pass_rb(PassArgs A) {
+__device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, const int b) {
   using C = typename CT<R>::T;
   static_assert(RB == 3, "layouts are encoded with three register bits");
   constexpr int NT = 1 << (MAXM - RB);
@@ -384,8 +384,6 @@ __global__ __launch_bounds__(1 << (MAXM - RB)) void tile_pass_rb(PassArgs A) {
   const int m = A.m;
   const int nloc = 1 << m;
   const bool active = tid < (nloc >> RB);
-  const uint64_t tile = blockIdx.x;
-  const int b = blockIdx.y;
   const uint64_t TM = A.tile_mask;
   const uint64_t full = (A.n_qubits >= 64) ? ~0ull : ((1ull << A.n_qubits) - 1);
   const uint64_t base = pdep64(tile, full & ~TM);
@@ -603,7 +601,7 @@ __global__ __launch_bounds__(1 << (MAXM - RB)) void tile_pass_rb(PassArgs A) {
       if (tid == 0) {
         double s = 0.0;
         for (int q = 0; q < (NT >= 64 ? NT / 64 : 1); ++q) s += red[q];
-        A.partials[((int64_t)b * A.n_pslots + ld(&O->pslot)) * (int64_t)gridDim.x + (int64_t)tile] = s;
+        A.partials[((int64_t)b * A.n_pslots + ld(&O->pslot)) * A.n_tiles + (int64_t)tile] = s;
       }
       acc = 0.0;
       __syncthreads();
@@ -619,6 +617,26 @@ __global__ __launch_bounds__(1 << (MAXM - RB)) void tile_pass_rb(PassArgs A) {
       if (ADJ) lam[xk[k]] = w[k];
     }
   }
+}
+
+template <typename R, int RB, int MAXM, bool ADJ>
+__global__ __launch_bounds__(1 << (MAXM - RB)) void tile_pass_rb(PassArgs A) {
+  rb_body<R, RB, MAXM, ADJ>(A, blockIdx.x, blockIdx.y);
+}
+
+// Many circuits in one launch: item i owns workgroups [prefix[i], prefix[i+1]); each
+// workgroup finds its item by binary search and runs that circuit's pass on one tile.
+template <typename R, int RB, int MAXM, bool ADJ>
+__global__ __launch_bounds__(1 << (MAXM - RB)) void tile_pass_rb_multi(const PassArgs* items, const uint32_t* prefix,
+                                                                       int n_items) {
+  const uint32_t w = blockIdx.x;
+  int lo = 0, hi = n_items;  // largest i with prefix[i] <= w
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ld(prefix + mid) <= w) lo = mid; else hi = mid;
+  }
+  const PassArgs A = items[lo];
+  rb_body<R, RB, MAXM, ADJ>(A, (uint64_t)(w - ld(prefix + lo)), 0);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -813,6 +831,99 @@ __global__ __launch_bounds__(256) void broadcast_state(void* dst_, int64_t bstri
 }
 
 // ------------------------------------------------------------------------------------------
+// Multi-circuit Pauli-sum pass in gather form: each thread owns an output index y and sums
+// c_k P_k psi over all terms, (P_k psi)[y] = i^{popcount(x_k & z_k)} (-1)^{popcount((y ^ x_k) & z_k)}
+// psi[y ^ x_k]; no two threads write the same lambda entry, so one launch covers every
+// term.  Workgroup w handles chunk (w - prefix[i]) of job i (CHUNK amplitudes).
+// ------------------------------------------------------------------------------------------
+template <typename R, int CHUNK>
+__global__ __launch_bounds__(256) void pauli_apply_multi(const PauliJob* jobs, const uint32_t* prefix, int n_jobs) {
+  using C = typename CT<R>::T;
+  __shared__ double red[2][4];
+  const uint32_t w = blockIdx.x;
+  int lo = 0, hi = n_jobs;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ld(prefix + mid) <= w) lo = mid; else hi = mid;
+  }
+  const PauliJob* J = jobs + lo;
+  const uint32_t chunk = w - ld(prefix + lo);
+  const C* psi = reinterpret_cast<const C*>(ld(&J->psi));
+  C* lam = reinterpret_cast<C*>(ld(&J->lam));
+  const uint64_t* xm = ld(&J->xmasks);
+  const uint64_t* zm = ld(&J->zmasks);
+  const double* cre = ld(&J->cre);
+  const double* cim = ld(&J->cim);
+  const int nt = ld(&J->n_terms);
+  const uint64_t N = 1ull << ld(&J->n_qubits);
+  double er = 0.0, ei = 0.0;
+  for (uint64_t y = (uint64_t)chunk * CHUNK + threadIdx.x; y < N && y < (uint64_t)(chunk + 1) * CHUNK; y += 256) {
+    double lr = 0.0, li = 0.0;
+    for (int k = 0; k < nt; ++k) {
+      const uint64_t x = y ^ ld(xm + k);
+      const C v = psi[x];
+      const double sgn = (__popcll(x & ld(zm + k)) & 1) ? -1.0 : 1.0;
+      const double ar = sgn * ld(cre + k), ai = sgn * ld(cim + k);
+      lr += ar * v.x - ai * v.y;
+      li += ar * v.y + ai * v.x;
+    }
+    const C py = psi[y];
+    er += (double)py.x * lr + (double)py.y * li;
+    ei += (double)py.x * li - (double)py.y * lr;
+    C o;
+    o.x = (R)lr;
+    o.y = (R)li;
+    lam[y] = o;
+  }
+  er = wave_sum(er);
+  ei = wave_sum(ei);
+  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = er; red[1][threadIdx.x >> 6] = ei; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* P = ld(&J->partials);
+    P[2 * chunk] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    P[2 * chunk + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
+// out[c] = sum of in[offs[c] + stride[c] * i] for i < lens[c], fixed order.
+__global__ __launch_bounds__(256) void reduce_segments(const double* in, const int64_t* offs, const int32_t* lens,
+                                                       const int32_t* strides, double* out) {
+  __shared__ double red[4];
+  const int c = blockIdx.x;
+  const int64_t o = ld(offs + c);
+  const int32_t len = ld(lens + c), st = ld(strides + c);
+  double s = 0.0;
+  for (int32_t i = threadIdx.x; i < len; i += 256) s += in[o + (int64_t)st * i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[c] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Fill states with |0...0>: job j covers 2^n[j] amplitudes at ptr[j] in CHUNK-sized pieces.
+template <typename R>
+__global__ __launch_bounds__(256) void set_zero_multi(void* const* ptrs, const int32_t* nq, const uint32_t* prefix,
+                                                      int n_jobs) {
+  using C = typename CT<R>::T;
+  const uint32_t w = blockIdx.x;
+  int lo = 0, hi = n_jobs;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ld(prefix + mid) <= w) lo = mid; else hi = mid;
+  }
+  C* psi = reinterpret_cast<C*>(ld(ptrs + lo));
+  const uint64_t N = 1ull << ld(nq + lo);
+  const uint64_t chunk = w - ld(prefix + lo);
+  for (uint64_t x = chunk * 4096 + threadIdx.x; x < N && x < (chunk + 1) * 4096; x += 256) {
+    C v;
+    v.x = x == 0 ? (R)1 : (R)0;
+    v.y = (R)0;
+    psi[x] = v;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Host launchers.
 // ------------------------------------------------------------------------------------------
 static inline unsigned stream_blocks(uint64_t work) {
@@ -867,6 +978,52 @@ static hipError_t rb_dispatch(int maxm, const PassArgs& A, uint64_t n_tiles, int
     case 13: return rb_launch_one<R, 13, ADJ>(A, grid, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <typename R, bool ADJ>
+static hipError_t rb_multi_dispatch(int maxm, const PassArgs* items, const uint32_t* prefix, int n_items,
+                                    uint32_t n_wg, hipStream_t s) {
+  switch (maxm) {
+#define QSV_MULTI(M)                                                                                   \
+  case M:                                                                                              \
+    if constexpr ((size_t)(2 * sizeof(R)) * ((size_t)1 << M) <= 131072) {                              \
+      tile_pass_rb_multi<R, 3, M, ADJ><<<n_wg, 1 << (M - 3), 0, s>>>(items, prefix, n_items);          \
+      return hipGetLastError();                                                                        \
+    }                                                                                                  \
+    return hipErrorInvalidValue;
+    QSV_MULTI(9) QSV_MULTI(10) QSV_MULTI(11) QSV_MULTI(12) QSV_MULTI(13)
+#undef QSV_MULTI
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_tile_pass_rb_multi(int dtype, bool adj, int maxm, const PassArgs* items, const uint32_t* prefix,
+                                     int n_items, uint32_t n_wg, hipStream_t s) {
+  if (dtype == 0) return adj ? rb_multi_dispatch<float, true>(maxm, items, prefix, n_items, n_wg, s)
+                             : rb_multi_dispatch<float, false>(maxm, items, prefix, n_items, n_wg, s);
+  return adj ? rb_multi_dispatch<double, true>(maxm, items, prefix, n_items, n_wg, s)
+             : rb_multi_dispatch<double, false>(maxm, items, prefix, n_items, n_wg, s);
+}
+
+hipError_t launch_pauli_apply_multi(int dtype, const PauliJob* jobs, const uint32_t* prefix, int n_jobs, uint32_t n_wg,
+                                    hipStream_t s) {
+  if (dtype == 0) pauli_apply_multi<float, kPauliChunk><<<n_wg, 256, 0, s>>>(jobs, prefix, n_jobs);
+  else pauli_apply_multi<double, kPauliChunk><<<n_wg, 256, 0, s>>>(jobs, prefix, n_jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_segments(const double* in, const int64_t* offs, const int32_t* lens, const int32_t* strides,
+                                  double* out, int ncols, hipStream_t s) {
+  if (ncols <= 0) return hipSuccess;
+  reduce_segments<<<(unsigned)ncols, 256, 0, s>>>(in, offs, lens, strides, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_zero_multi(int dtype, void* const* ptrs, const int32_t* nq, const uint32_t* prefix, int n_jobs,
+                                 uint32_t n_wg, hipStream_t s) {
+  if (dtype == 0) set_zero_multi<float><<<n_wg, 256, 0, s>>>(ptrs, nq, prefix, n_jobs);
+  else set_zero_multi<double><<<n_wg, 256, 0, s>>>(ptrs, nq, prefix, n_jobs);
+  return hipGetLastError();
 }
 
 hipError_t launch_tile_pass_rb(int dtype, bool adj, int maxm, const PassArgs& A, uint64_t n_tiles, int batch,

@@ -87,6 +87,21 @@ struct PassArgs {
   int32_t      n_pslots;
   int32_t      lr0;           // register-blocked passes: local register mask at load time
   int32_t      pad0;
+  int64_t      n_tiles;       // tiles of this state (column length of partials)
+};
+
+// One circuit's share of a multi-circuit Pauli-sum pass: lambda = H psi and the
+// expectation partials of 2^n amplitudes, in chunks of one workgroup each.
+struct PauliJob {
+  const void*     psi;
+  void*           lam;
+  const uint64_t* xmasks;     // terms
+  const uint64_t* zmasks;
+  const double*   cre;        // coefficient * i^{popcount(x & z)}
+  const double*   cim;
+  double*         partials;   // two doubles (re, im) per chunk
+  int32_t         n_terms;
+  int32_t         n_qubits;
 };
 
 // Pauli-sum pass over one group of terms sharing an x-mask.

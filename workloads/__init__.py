@@ -241,6 +241,7 @@ def random_state(n_qubits, rng, dtype=np.complex128):
 # ----------------------------------------------------------------------------------------
 # The benchmark workloads, by name.
 # ----------------------------------------------------------------------------------------
+UNEVEN512 = dict(n_circuits=512, n_min=8, n_max=20, depth_min=2, depth_max=10, n_terms=50, seed=512)
 HEA10 = dict(n_qubits=10, layers=4, param_seed=1)
 BRICK30 = dict(n_qubits=30, depth=20, seed=2406)
 QAOA24 = dict(n_qubits=24, degree=3, graph_seed=17248, p=8, batch=64, param_seed=8)
@@ -265,3 +266,23 @@ def qaoa_workload(n_qubits=QAOA24["n_qubits"], p=QAOA24["p"], batch=QAOA24["batc
     ham = maxcut_hamiltonian(edges)
     params = uniform_params(2 * p, param_seed, 0.0, np.pi, batch=batch)
     return circ, ham, params, edges
+
+
+def uneven_batch_workload(n_circuits=UNEVEN512["n_circuits"], n_min=UNEVEN512["n_min"], n_max=UNEVEN512["n_max"],
+                          depth_min=UNEVEN512["depth_min"], depth_max=UNEVEN512["depth_max"],
+                          n_terms=UNEVEN512["n_terms"], seed=UNEVEN512["seed"]):
+    """Hardware-efficient ansaetze with qubit counts uniform in [n_min, n_max] and depths
+    uniform in [depth_min, depth_max]; each with its own Hamiltonian of n_terms random
+    1-4-local Pauli strings (qubits without replacement, X/Y/Z uniform, N(0,1)
+    coefficients) and its own angles uniform in [0, 2 pi).  Returns (circuits,
+    hamiltonians, params) with params concatenated in circuit order."""
+    rng = np.random.default_rng(seed)
+    circs, hams, params = [], [], []
+    for _ in range(n_circuits):
+        n = int(rng.integers(n_min, n_max + 1))
+        d = int(rng.integers(depth_min, depth_max + 1))
+        c = hea_circuit(n, d)
+        circs.append(c)
+        hams.append(random_pauli_sum(n, n_terms, rng, max_locality=4, identity_term=False))
+        params.append(rng.uniform(0.0, 2 * np.pi, n_params_of(c)))
+    return circs, hams, np.concatenate(params)
