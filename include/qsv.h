@@ -237,6 +237,35 @@ int qsv_batch_autotune(qsv_batch* b, const double* params, int32_t* out_tile);
 /* out_E[i] = <H_i> of circuit i; out_grad (may be NULL) has the layout of params. */
 int qsv_batch_expectation_and_grad(qsv_batch* b, const double* params, double* out_E, double* out_grad);
 
+/* ---- learned warm start for QAOA MaxCut -------------------------------------------------
+ * A 2-layer message-passing network (hidden 64, fp32) mapping a 16-node graph to p = 6
+ * QAOA angles (6 gamma then 6 beta in the layer convention of section 6.2), as a correction
+ * to a given ramp schedule: angles = ramp + readout(graph).  Node features are
+ * [1, degree / 4, triangles / 3]; layer l: Z = H Ws + (A H) Wn / 4 + b, H' = relu(Z);
+ * readout: mean over nodes, then a linear map to 12 outputs.  Parameters (float32, row
+ * major, in this order): W1s[3][64], W1n[3][64], b1[64], W2s[64][64], W2n[64][64], b2[64],
+ * Wo[64][12], bo[12].  Graphs are given as 16 neighbour bit masks each (uint16, no self
+ * loops).  Training minimizes the mean over graphs of |angles - labels|^2 / 12 with Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8), all on the device. */
+#define QSV_MPNN_NODES 16
+#define QSV_MPNN_FEATURES 3
+#define QSV_MPNN_HIDDEN 64
+#define QSV_MPNN_OUTPUTS 12
+#define QSV_MPNN_PARAMS 9484
+typedef struct qsv_mpnn qsv_mpnn;
+int qsv_mpnn_create(const float* init_params, qsv_mpnn** out);
+int qsv_mpnn_destroy(qsv_mpnn* m);
+int qsv_mpnn_get_params(const qsv_mpnn* m, float* out_params);
+/* out_angles[n_graphs][12] */
+int qsv_mpnn_predict(qsv_mpnn* m, const uint16_t* adjacency, size_t n_graphs, const double* ramp,
+                     double* out_angles);
+/* loss and its gradient with respect to the parameters (no update) */
+int qsv_mpnn_loss_and_grad(qsv_mpnn* m, const uint16_t* adjacency, size_t n_graphs, const double* ramp,
+                           const double* labels, double* out_loss, float* out_grad);
+/* one Adam step on this minibatch; *out_loss (may be NULL) is the loss before the step */
+int qsv_mpnn_train_step(qsv_mpnn* m, const uint16_t* adjacency, size_t n_graphs, const double* ramp,
+                        const double* labels, double lr, double* out_loss);
+
 /* ---- profiling ----------------------------------------------------------------------- */
 /* Kernel classes timed when QSV_OPT_PROFILE is 1. */
 enum qsv_kernel_class {

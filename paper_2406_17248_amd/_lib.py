@@ -37,7 +37,10 @@ EXPORTED = (
     "qsv_forward_batch", "qsv_backward_batch",
     "qsv_batch_create", "qsv_batch_destroy", "qsv_batch_info", "qsv_batch_set_tile", "qsv_batch_autotune",
     "qsv_batch_expectation_and_grad",
+    "qsv_mpnn_create", "qsv_mpnn_destroy", "qsv_mpnn_get_params", "qsv_mpnn_predict", "qsv_mpnn_loss_and_grad",
+    "qsv_mpnn_train_step",
 )
+MPNN_PARAMS, MPNN_NODES, MPNN_OUTPUTS = 9484, 16, 12
 
 
 class qsv_gate(C.Structure):
@@ -127,6 +130,12 @@ def lib():
             "qsv_batch_set_tile": ([vp, i32], C.c_int),
             "qsv_batch_autotune": ([vp, dp, C.POINTER(i32)], C.c_int),
             "qsv_batch_expectation_and_grad": ([vp, dp, dp, dp], C.c_int),
+            "qsv_mpnn_create": ([C.POINTER(C.c_float), C.POINTER(vp)], C.c_int),
+            "qsv_mpnn_destroy": ([vp], C.c_int),
+            "qsv_mpnn_get_params": ([vp, C.POINTER(C.c_float)], C.c_int),
+            "qsv_mpnn_predict": ([vp, C.POINTER(C.c_uint16), sz, dp, dp], C.c_int),
+            "qsv_mpnn_loss_and_grad": ([vp, C.POINTER(C.c_uint16), sz, dp, dp, dp, C.POINTER(C.c_float)], C.c_int),
+            "qsv_mpnn_train_step": ([vp, C.POINTER(C.c_uint16), sz, dp, dp, C.c_double, dp], C.c_int),
             "qsv_forward_batch": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), dp, sz, sz, dp],
                                   C.c_int),
             "qsv_backward_batch": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), dp, sz, sz, dp, dp],
@@ -481,3 +490,62 @@ def qsv_batch_expectation_and_grad(b, params):
     g = np.zeros(max(p.size, 1))
     check(lib().qsv_batch_expectation_and_grad(b.handle, _dp(p), _dp(E), _dp(g)))
     return E, g[:p.size]
+
+
+# ------------------------------------------------------------------------------------------
+# Warm-start network
+# ------------------------------------------------------------------------------------------
+def _u16(a):
+    a = np.ascontiguousarray(a, dtype=np.uint16)
+    return a, a.ctypes.data_as(C.POINTER(C.c_uint16))
+
+
+class Mpnn:
+    """The warm-start network on the device (qsv_mpnn*)."""
+
+    def __init__(self, init_params):
+        w = np.ascontiguousarray(init_params, dtype=np.float32)
+        if w.size != MPNN_PARAMS:
+            raise ValueError(f"expected {MPNN_PARAMS} parameters")
+        h = C.c_void_p()
+        check(lib().qsv_mpnn_create(w.ctypes.data_as(C.POINTER(C.c_float)), C.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        try:
+            if self.handle and _lib is not None:
+                _lib.qsv_mpnn_destroy(self.handle)
+                self.handle = C.c_void_p(None)
+        except Exception:
+            pass
+
+    def params(self):
+        out = np.zeros(MPNN_PARAMS, dtype=np.float32)
+        check(lib().qsv_mpnn_get_params(self.handle, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def predict(self, adjacency, ramp):
+        a, ap = _u16(adjacency)
+        n = a.shape[0]
+        r = np.ascontiguousarray(ramp, dtype=np.float64)
+        out = np.zeros((n, MPNN_OUTPUTS))
+        check(lib().qsv_mpnn_predict(self.handle, ap, n, _dp(r), _dp(out)))
+        return out
+
+    def loss_and_grad(self, adjacency, ramp, labels):
+        a, ap = _u16(adjacency)
+        r = np.ascontiguousarray(ramp, dtype=np.float64)
+        lab = np.ascontiguousarray(labels, dtype=np.float64)
+        loss = C.c_double()
+        g = np.zeros(MPNN_PARAMS, dtype=np.float32)
+        check(lib().qsv_mpnn_loss_and_grad(self.handle, ap, a.shape[0], _dp(r), _dp(lab), C.byref(loss),
+                                           g.ctypes.data_as(C.POINTER(C.c_float))))
+        return loss.value, g
+
+    def train_step(self, adjacency, ramp, labels, lr):
+        a, ap = _u16(adjacency)
+        r = np.ascontiguousarray(ramp, dtype=np.float64)
+        lab = np.ascontiguousarray(labels, dtype=np.float64)
+        loss = C.c_double()
+        check(lib().qsv_mpnn_train_step(self.handle, ap, a.shape[0], _dp(r), _dp(lab), float(lr), C.byref(loss)))
+        return loss.value

@@ -286,3 +286,36 @@ def uneven_batch_workload(n_circuits=UNEVEN512["n_circuits"], n_min=UNEVEN512["n
         hams.append(random_pauli_sum(n, n_terms, rng, max_locality=4, identity_term=False))
         params.append(rng.uniform(0.0, 2 * np.pi, n_params_of(c)))
     return circs, hams, np.concatenate(params)
+
+
+# ----------------------------------------------------------------------------------------
+# Learned warm start: 16-node graphs, half random 3-regular, half Erdos-Renyi G(16, 0.3).
+# ----------------------------------------------------------------------------------------
+WARMSTART = dict(n_nodes=16, p=6, n_train=20000, n_test=1000, seed=616)
+
+
+def warmstart_graphs(n_graphs, seed, n_nodes=WARMSTART["n_nodes"]):
+    """Edge lists: even indices random 3-regular, odd indices G(n, 0.3) (edgeless draws
+    are redrawn)."""
+    import networkx as nx
+    rng = np.random.default_rng(seed)
+    graphs = []
+    for i in range(n_graphs):
+        s = int(rng.integers(0, 2**31 - 1))
+        if i % 2 == 0:
+            g = nx.random_regular_graph(3, n_nodes, seed=s)
+        else:
+            g = nx.gnp_random_graph(n_nodes, 0.3, seed=s)
+            while g.number_of_edges() == 0:
+                s += 1
+                g = nx.gnp_random_graph(n_nodes, 0.3, seed=s)
+        graphs.append(sorted(tuple(sorted(e)) for e in g.edges))
+    return graphs
+
+
+def linear_ramp(p=WARMSTART["p"], d_gamma=1.0, d_beta=0.5):
+    """Linear-ramp QAOA schedule gamma_l = d_gamma (l+1)/p, beta_l = d_beta (1 - l/p) for
+    U = prod_l exp(-i beta_l B) exp(-i gamma_l C), written in the layer convention of
+    qaoa_circuit (exp(-i g' Z Z), RX(b')): g' = -gamma/2, b' = 2 beta."""
+    l = np.arange(p)
+    return np.concatenate([-0.5 * d_gamma * (l + 1) / p, 2.0 * d_beta * (1 - l / p)])
