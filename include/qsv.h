@@ -206,6 +206,22 @@ int qsv_backward_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* 
 int qsv_expectation_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h,
                           const double* params, size_t batch, size_t n_params, double* out_E);
 
+/* General form E = <phi| U_l^dag H U_r |psi> (section 2.6, get_expectation with a left
+ * circuit and state; section 4.1, get_expectation_with_grad with circ_left), complex, with
+ * its complex derivatives: grad_r[2k], grad_r[2k+1] = Re, Im of dE/dparams_r[k] and grad_l
+ * likewise for params_l (E is conjugate-linear in U_l phi).  c_l NULL means U_l = I.  phi may
+ * be psi; both states are left unchanged.  out_E receives (Re E, Im E).  grad_r / grad_l may
+ * be NULL.  Uses four state-sized workspaces of two amplitudes vectors each. */
+int qsv_expectation_general(qsv_state* psi, const qsv_circuit* c_r, const double* params_r, size_t n_r,
+                            const qsv_state* phi, const qsv_circuit* c_l, const double* params_l, size_t n_l,
+                            const qsv_pauli_sum* h, double* out_E, double* grad_r, double* grad_l);
+
+/* Several Hamiltonians of one circuit at once (section 4.1: outputs [n_ham] and
+ * [n_ham][n_params]): one forward sweep, then lambda_k = H_k psi and the adjoint sweep for
+ * all Hamiltonians as batch items.  The state is unchanged. */
+int qsv_expectation_and_grad_multi(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* hams, size_t n_hams,
+                                   const double* params, size_t n_params, double* out_E, double* out_grad);
+
 /* Gradient by the two-term parameter-shift rule, evaluated on the GPU with the same
  * kernels (2 energies per parameterized angle occurrence).  Comparator for the adjoint
  * method.  QSV_ENOTSUP if a parameterized gate has controls. */

@@ -307,6 +307,60 @@ def grad_finite_diff(circ, terms, params, h=1e-6, psi0=None):
 
 
 # --------------------------------------------------------------------------------------
+# General form E = <phi| U_l^dag H U_r |psi> (section 2.6, get_expectation with a left
+# circuit and state; section 4.1, the gradient operator with circ_left).
+# --------------------------------------------------------------------------------------
+def expectation_general(circ_r, params_r, psi, circ_l, params_l, phi, terms):
+    n = circ_r["n_qubits"]
+    psi_r = simulate(circ_r, params_r, psi)
+    phi_l = simulate(circ_l, params_l, phi) if circ_l is not None else np.array(phi, dtype=np.complex128)
+    return np.vdot(phi_l, apply_pauli_sum(psi_r, n, terms))
+
+
+def _simulate_replacing(circ, params, psi0, k, a):
+    """The circuit with gate k replaced by d(gate)/d(angle a): the derivative matrix on the
+    control-satisfied subspace and zero elsewhere."""
+    n = circ["n_qubits"]
+    psi = np.array(psi0, dtype=np.complex128, copy=True)
+    for i, g in enumerate(circ["gates"]):
+        if i != k:
+            apply_gate(psi, n, g, params)
+            continue
+        dU = gate_angle_derivs(g, params)[a]
+        psi = _apply_controlled_deriv(psi, n, dU, g) if g["ctrls"] else apply_matrix(psi, n, dU, g["targets"], ())
+    return psi
+
+
+def grad_general(circ_r, params_r, psi, circ_l, params_l, phi, terms):
+    """(E, dE/dparams_r, dE/dparams_l) as complex numbers, by the definition: E is linear in
+    every gate of U_r and conjugate-linear in every gate of U_l, so each parameter's
+    derivative is the sum over its occurrences of coeff * E with that gate replaced by its
+    derivative matrix."""
+    n = circ_r["n_qubits"]
+    params_r = np.asarray(params_r, dtype=np.float64)
+    psi_r = simulate(circ_r, params_r, psi)
+    phi_l = simulate(circ_l, params_l, phi) if circ_l is not None else np.array(phi, dtype=np.complex128)
+    E = np.vdot(phi_l, apply_pauli_sum(psi_r, n, terms))
+    g_r = np.zeros(params_r.size, dtype=np.complex128)
+    for k, g in enumerate(circ_r["gates"]):
+        for a, (i, coeff, _) in enumerate(g["params"]):
+            if i >= 0:
+                v = _simulate_replacing(circ_r, params_r, psi, k, a)
+                g_r[i] += coeff * np.vdot(phi_l, apply_pauli_sum(v, n, terms))
+    g_l = None
+    if circ_l is not None:
+        params_l = np.asarray(params_l, dtype=np.float64)
+        chi = apply_pauli_sum(psi_r, n, terms)
+        g_l = np.zeros(params_l.size, dtype=np.complex128)
+        for k, g in enumerate(circ_l["gates"]):
+            for a, (i, coeff, _) in enumerate(g["params"]):
+                if i >= 0:
+                    v = _simulate_replacing(circ_l, params_l, phi, k, a)
+                    g_l[i] += coeff * np.vdot(v, chi)
+    return E, g_r, g_l
+
+
+# --------------------------------------------------------------------------------------
 # Brute force: the full 2^n x 2^n unitary from Kronecker products (small n only).
 # --------------------------------------------------------------------------------------
 def _kron_chain(ops_by_qubit, n):

@@ -38,7 +38,7 @@ EXPORTED = (
     "qsv_batch_create", "qsv_batch_destroy", "qsv_batch_info", "qsv_batch_set_tile", "qsv_batch_autotune",
     "qsv_batch_expectation_and_grad",
     "qsv_mpnn_create", "qsv_mpnn_destroy", "qsv_mpnn_get_params", "qsv_mpnn_predict", "qsv_mpnn_loss_and_grad",
-    "qsv_mpnn_train_step",
+    "qsv_mpnn_train_step", "qsv_expectation_general", "qsv_expectation_and_grad_multi",
 )
 MPNN_PARAMS, MPNN_NODES, MPNN_OUTPUTS = 9484, 16, 12
 
@@ -136,6 +136,10 @@ def lib():
             "qsv_mpnn_predict": ([vp, C.POINTER(C.c_uint16), sz, dp, dp], C.c_int),
             "qsv_mpnn_loss_and_grad": ([vp, C.POINTER(C.c_uint16), sz, dp, dp, dp, C.POINTER(C.c_float)], C.c_int),
             "qsv_mpnn_train_step": ([vp, C.POINTER(C.c_uint16), sz, dp, dp, C.c_double, dp], C.c_int),
+            "qsv_expectation_general": ([vp, C.POINTER(qsv_circuit), dp, sz, vp, C.POINTER(qsv_circuit), dp, sz,
+                                         C.POINTER(qsv_pauli_sum), dp, dp, dp], C.c_int),
+            "qsv_expectation_and_grad_multi": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), sz, dp, sz,
+                                                dp, dp], C.c_int),
             "qsv_forward_batch": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), dp, sz, sz, dp],
                                   C.c_int),
             "qsv_backward_batch": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), dp, sz, sz, dp, dp],
@@ -381,6 +385,34 @@ def qsv_expectation_batch(s, circuit, hamiltonian, params):
     E = np.zeros(B)
     check(lib().qsv_expectation_batch(s.handle, c.ptr, h.ptr, _dp(p), B, P, _dp(E)))
     return E
+
+
+def qsv_expectation_general(psi, circuit_r, params_r, phi, circuit_l, params_l, hamiltonian, grads=True):
+    """E = <phi|U_l^dag H U_r|psi> (complex) and complex gradients for both circuits
+    (circuit_l None: U_l = I)."""
+    cr, h = _circuit(circuit_r), _pauli(hamiltonian)
+    cl = _circuit(circuit_l) if circuit_l is not None else None
+    pr, pl = _params(params_r), _params(params_l)
+    E = np.zeros(2)
+    gr = np.zeros(2 * max(pr.size, 1))
+    gl = np.zeros(2 * max(pl.size, 1))
+    check(lib().qsv_expectation_general(psi.handle, cr.ptr, _dp(pr), pr.size, phi.handle,
+                                        cl.ptr if cl is not None else None, _dp(pl), pl.size, h.ptr, _dp(E),
+                                        _dp(gr) if grads else None, _dp(gl) if grads and cl is not None else None))
+    g_r = gr[:2 * pr.size].view(np.complex128) if grads else None
+    g_l = gl[:2 * pl.size].view(np.complex128) if grads and cl is not None else None
+    return complex(E[0], E[1]), g_r, g_l
+
+
+def qsv_expectation_and_grad_multi(s, circuit, hamiltonians, params):
+    c = _circuit(circuit)
+    hs = [_pauli(h) for h in hamiltonians]
+    arr = (qsv_pauli_sum * len(hs))(*[h.h for h in hs])
+    p = _params(params)
+    E = np.zeros(len(hs))
+    g = np.zeros((len(hs), max(p.size, 1)))
+    check(lib().qsv_expectation_and_grad_multi(s.handle, c.ptr, arr, len(hs), _dp(p), p.size, _dp(E), _dp(g)))
+    return E, g[:, :p.size]
 
 
 def qsv_forward_batch(s, circuit, hamiltonian, params):

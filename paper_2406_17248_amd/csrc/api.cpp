@@ -44,7 +44,7 @@ struct qsv_state {
   double prof_ms[QSV_K_COUNT] = {0, 0, 0, 0, 0};
   int64_t prof_n[QSV_K_COUNT] = {0, 0, 0, 0, 0};
   double prof_bytes[QSV_K_COUNT] = {0, 0, 0, 0, 0};
-  DevBuf ws_psi, ws_lam, upload, partials, gpart, outbuf, pauli;
+  DevBuf ws_psi, ws_lam, ws_aux1, ws_aux2, upload, partials, gpart, outbuf, pauli;
   // pinned staging for uploads and downloads, guarded by an event
   void* stage = nullptr;
   size_t stage_bytes = 0;
@@ -364,6 +364,40 @@ qsv_state* check_state(const qsv_state* s) {
 
 // Energies (and optionally gradients) of `batch` bound tables.  Shared by the batch entry
 // points and the parameter-shift comparator.
+// Adjoint reverse sweep of plan adj over (psi, lam) batch items; writes the reduced
+// gradient columns [batch][n_pslots] to d_cols (device).
+void run_adjoint(qsv_state* s, const Plan& adj, const Uploaded& u, void* psi, void* lam, int64_t bstride, int batch,
+                 double* d_cols) {
+  const int P = adj.n_pslots;
+  if (P == 0 || adj.passes.empty()) return;
+  const uint64_t tiles = 1ull << (s->n - adj.passes[0].m);
+  s->gpart.reserve((size_t)batch * P * tiles * sizeof(double));
+  for (const DevPass& ap : adj.passes) {
+    PassArgs A{};
+    A.psi = psi;
+    A.lam = lam;
+    A.src = nullptr;
+    A.bstride = bstride;
+    A.src_bstride = 0;
+    A.ops = u.ops + ap.op_first;
+    A.diag = u.diag;
+    A.edges = u.edges;
+    A.ctab = u.ctab;
+    A.ctab_bstride = u.ctab_stride;
+    A.partials = static_cast<double*>(s->gpart.p) + (size_t)ap.pslot_first * tiles;
+    A.tile_mask = ap.tile_mask;
+    A.n_ops = ap.op_count;
+    A.n_qubits = s->n;
+    A.m = ap.m;
+    A.n_pslots = P;
+    const double bytes = 4.0 * (double)batch * (double)s->namps() * (double)s->amp_bytes();
+    timed(s, QSV_K_TILE_ADJOINT, bytes, [&] { return launch_pass(s, ap, A, batch, true); }, "adjoint tile pass");
+  }
+  hip_check(launch_reduce_columns(static_cast<double*>(s->gpart.p), (int64_t)tiles, (int64_t)batch * P, d_cols,
+                                  s->stream),
+            "reduce gradients");
+}
+
 // run_fwd = false: the evolved states of an earlier forward-only call are still in the
 // workspace (qsv_backward_batch), so only lambda and the reverse sweep run.
 void energies_and_grads(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h, const Plan& fwd,
@@ -391,40 +425,7 @@ void energies_and_grads(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum*
   s->outbuf.reserve((ne + ng + 1) * sizeof(double));
   double* d_out = static_cast<double*>(s->outbuf.p);
   run_pauli(s, dp, s->ws_psi.p, adj ? s->ws_lam.p : nullptr, bstride, batch, d_out);
-  if (adj && P > 0) {
-    uint64_t max_tiles = 1;
-    for (const DevPass& ap : adj->passes) max_tiles = std::max<uint64_t>(max_tiles, 1ull << (s->n - ap.m));
-    s->gpart.reserve((size_t)batch * P * max_tiles * sizeof(double));
-    const uint64_t tiles = 1ull << (s->n - adj->passes[0].m);
-    for (const DevPass& ap : adj->passes) {
-      PassArgs A{};
-      A.psi = s->ws_psi.p;
-      A.lam = s->ws_lam.p;
-      A.src = nullptr;
-      A.bstride = bstride;
-      A.src_bstride = 0;
-      A.ops = up[1].ops + ap.op_first;
-      A.diag = up[1].diag;
-      A.edges = up[1].edges;
-      A.ctab = up[1].ctab;
-      A.ctab_bstride = up[1].ctab_stride;
-      A.partials = static_cast<double*>(s->gpart.p) + (size_t)ap.pslot_first * tiles;
-      A.tile_mask = ap.tile_mask;
-      A.n_ops = ap.op_count;
-      A.n_qubits = s->n;
-      A.m = ap.m;
-      A.n_pslots = P;
-      const double bytes = 4.0 * (double)batch * (double)s->namps() * (double)s->amp_bytes();
-      timed(s, QSV_K_TILE_ADJOINT, bytes,
-            [&] { return launch_pass(s, ap, A, batch, true); },
-            "adjoint tile pass");
-    }
-    hip_check(launch_reduce_columns(static_cast<double*>(s->gpart.p), (int64_t)tiles, (int64_t)ng, d_out + ne,
-                                    s->stream),
-              "reduce gradients");
-  } else if (adj) {
-    // no gradient slots: still run the reverse sweep? nothing depends on it
-  }
+  if (adj && P > 0) run_adjoint(s, *adj, up[1], s->ws_psi.p, s->ws_lam.p, bstride, batch, d_out + ne);
   double* host = static_cast<double*>(stage_acquire(s, (ne + ng + 1) * sizeof(double)));
   hip_check(hipMemcpyAsync(host, d_out, (ne + ng) * sizeof(double), hipMemcpyDeviceToHost, s->stream), "download");
   hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
@@ -507,6 +508,8 @@ int qsv_state_destroy(qsv_state* s) {
     if (s->owned && s->psi) (void)hipFree(s->psi);
     s->ws_psi.release();
     s->ws_lam.release();
+    s->ws_aux1.release();
+    s->ws_aux2.release();
     s->upload.release();
     s->partials.release();
     s->gpart.release();
@@ -778,6 +781,169 @@ int qsv_backward_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* 
       for (size_t k = 0; k < n_params; ++k) g[k] = 0.0;
       for (int k = 0; k < P; ++k) g[adj.pslot_param[k]] += gcols[b * P + k];
       for (size_t k = 0; k < n_params; ++k) g[k] *= dE_weights[b];
+    }
+  });
+}
+
+int qsv_expectation_general(qsv_state* psi, const qsv_circuit* c_r, const double* params_r, size_t n_r,
+                            const qsv_state* phi, const qsv_circuit* c_l, const double* params_l, size_t n_l,
+                            const qsv_pauli_sum* h, double* out_E, double* grad_r, double* grad_l) {
+  return guarded([&] {
+    check_state(psi);
+    check_state(phi);
+    if (!out_E) fail(QSV_EINVAL, "out_E is NULL");
+    if (psi->dtype != phi->dtype) fail(QSV_EDTYPE, "dtype mismatch");
+    if (psi->n != phi->n) fail(QSV_EINVAL, "n_qubits mismatch");
+    if (n_r && !params_r) fail(QSV_EINVAL, "params_r is NULL");
+    if (n_l && !params_l) fail(QSV_EINVAL, "params_l is NULL");
+    validate_circuit(c_r, n_r, psi->n);
+    if (c_l) validate_circuit(c_l, n_l, psi->n);
+    validate_pauli_sum(h, psi->n);
+    qsv_state* s = psi;
+    set_device(s);
+    s->fwd_token.clear();
+    const uint64_t N = s->namps();
+    const int64_t bs = (int64_t)N;
+    const size_t pair = 2 * N * s->amp_bytes();
+    s->ws_psi.reserve(pair);
+    s->ws_lam.reserve(pair);
+    s->ws_aux1.reserve(pair);
+    s->ws_aux2.reserve(pair);
+    const Plan& fr = get_plan(s, c_r, false, true);
+    const Plan* ar = grad_r ? &get_plan(s, c_r, true, true) : nullptr;
+    const Plan* fl = c_l ? &get_plan(s, c_l, false, true) : nullptr;
+    const Plan* al = (c_l && grad_l) ? &get_plan(s, c_l, true, true) : nullptr;
+    auto bind2 = [&](const Plan* p, const qsv_circuit* c, const double* prm) {
+      std::vector<cplx> t(p ? 2 * (size_t)p->ctab_size : 0);
+      if (p) {
+        bind_ctab(*p, c, prm, nullptr, 0, t.data());
+        bind_ctab(*p, c, prm, nullptr, 0, t.data() + p->ctab_size);
+      }
+      return t;
+    };
+    const std::vector<cplx> t_fr = bind2(&fr, c_r, params_r), t_ar = bind2(ar, c_r, params_r),
+                            t_fl = bind2(fl, c_l, params_l), t_al = bind2(al, c_l, params_l);
+    const Plan* plans[4] = {&fr, ar, fl, al};
+    const std::vector<cplx>* tabs[4] = {&t_fr, &t_ar, &t_fl, &t_al};
+    UploadReq req[4];
+    int map[4], nreq = 0;
+    for (int k = 0; k < 4; ++k) {
+      map[k] = -1;
+      if (plans[k]) {
+        map[k] = nreq;
+        req[nreq++] = UploadReq{plans[k], tabs[k], 2};
+      }
+    }
+    Uploaded up[4];
+    upload_plans(s, req, nreq, up);
+    char* P1 = static_cast<char*>(s->ws_psi.p);   // U_r psi (two copies)
+    char* L1 = static_cast<char*>(s->ws_lam.p);   // H U_l phi, i H U_l phi
+    char* P2 = static_cast<char*>(s->ws_aux1.p);  // U_l phi (two copies)
+    char* L2 = static_cast<char*>(s->ws_aux2.p);  // H U_r psi, i H U_r psi
+    const size_t one = N * s->amp_bytes();
+    run_forward(s, fr, up[map[0]], P1, bs, psi->psi, 0, 2);
+    if (fl) run_forward(s, *fl, up[map[2]], P2, bs, phi->psi, 0, 2);
+    else hip_check(launch_broadcast_state(s->dtype, P2, bs, 2, phi->psi, s->n, s->stream), "copy phi");
+    DevPauli dp = upload_pauli(s, h, s->pauli);
+    const int G = (int)dp.groups.size();
+    const int Pr = ar ? ar->n_pslots : 0, Pl = al ? al->n_pslots : 0;
+    const size_t o_tmp = 0, o_E = 2 * (size_t)G, o_r = o_E + 2, o_l = o_r + 2 * (size_t)Pr, total = o_l + 2 * (size_t)Pl;
+    s->outbuf.reserve((total + 1) * sizeof(double));
+    double* d_out = static_cast<double*>(s->outbuf.p);
+    run_pauli(s, dp, P1, L2, bs, 1, d_out + o_tmp);  // chi = H U_r psi
+    run_pauli(s, dp, P2, L1, bs, 1, d_out + o_tmp);  // lambda_r = H U_l phi
+    const unsigned ib = inner_blocks(s->n);
+    s->partials.reserve(2 * ib * sizeof(double));
+    hip_check(launch_inner_product(s->dtype, P2, L2, s->n, static_cast<double*>(s->partials.p), s->stream), "inner");
+    hip_check(launch_reduce_columns(static_cast<double*>(s->partials.p), ib, 2, d_out + o_E, s->stream), "reduce");
+    hip_check(launch_scale_copy(s->dtype, L1 + one, L1, s->n, 0.0, 1.0, s->stream), "i lambda");
+    hip_check(launch_scale_copy(s->dtype, L2 + one, L2, s->n, 0.0, 1.0, s->stream), "i chi");
+    if (ar) run_adjoint(s, *ar, up[map[1]], P1, L1, bs, 2, d_out + o_r);
+    if (al) run_adjoint(s, *al, up[map[3]], P2, L2, bs, 2, d_out + o_l);
+    double* host = static_cast<double*>(stage_acquire(s, (total + 1) * sizeof(double)));
+    hip_check(hipMemcpyAsync(host, d_out, total * sizeof(double), hipMemcpyDeviceToHost, s->stream), "download");
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    out_E[0] = host[o_E];
+    out_E[1] = host[o_E + 1];
+    // Im<lam|G|psi> with lam and with i lam give the two parts of the derivative:
+    // right circuit dE = (I1 + i I2) / 2; left circuit dE = (I1 - i I2) / 2.
+    if (grad_r) {
+      for (size_t k = 0; k < 2 * n_r; ++k) grad_r[k] = 0.0;
+      for (int k = 0; k < Pr; ++k) {
+        const int prm = ar->pslot_param[k];
+        grad_r[2 * prm] += 0.5 * host[o_r + k];
+        grad_r[2 * prm + 1] += 0.5 * host[o_r + Pr + k];
+      }
+    }
+    if (grad_l) {
+      for (size_t k = 0; k < 2 * n_l; ++k) grad_l[k] = 0.0;
+      for (int k = 0; k < Pl; ++k) {
+        const int prm = al->pslot_param[k];
+        grad_l[2 * prm] += 0.5 * host[o_l + k];
+        grad_l[2 * prm + 1] -= 0.5 * host[o_l + Pl + k];
+      }
+    }
+  });
+}
+
+int qsv_expectation_and_grad_multi(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* hams, size_t n_hams,
+                                   const double* params, size_t n_params, double* out_E, double* out_grad) {
+  return guarded([&] {
+    check_state(s);
+    if (n_hams < 1 || n_hams > 65535) fail(QSV_ERANGE, "n_hams must be in [1, 65535]");
+    if (!hams || !out_E) fail(QSV_EINVAL, "NULL argument");
+    if (n_params && (!params || !out_grad)) fail(QSV_EINVAL, "params / out_grad are NULL");
+    validate_circuit(c, n_params, s->n);
+    for (size_t k = 0; k < n_hams; ++k) validate_pauli_sum(&hams[k], s->n);
+    set_device(s);
+    s->fwd_token.clear();
+    const uint64_t N = s->namps();
+    const int64_t bs = (int64_t)N;
+    const size_t one = N * s->amp_bytes();
+    s->ws_psi.reserve(n_hams * one);
+    s->ws_lam.reserve(n_hams * one);
+    const Plan& fwd = get_plan(s, c, false, true);
+    const Plan& adj = get_plan(s, c, true, true);
+    std::vector<cplx> tf(fwd.ctab_size), ta((size_t)n_hams * adj.ctab_size);
+    bind_ctab(fwd, c, params, nullptr, 0, tf.data());
+    for (size_t k = 0; k < n_hams; ++k) bind_ctab(adj, c, params, nullptr, 0, ta.data() + k * adj.ctab_size);
+    UploadReq req[2] = {{&fwd, &tf, 1}, {&adj, &ta, (int)n_hams}};
+    Uploaded up[2];
+    upload_plans(s, req, 2, up);
+    char* P = static_cast<char*>(s->ws_psi.p);
+    char* L = static_cast<char*>(s->ws_lam.p);
+    run_forward(s, fwd, up[0], P, bs, s->psi, 0, 1);
+    if (n_hams > 1)
+      hip_check(launch_broadcast_state(s->dtype, P + one, bs, (int)n_hams - 1, P, s->n, s->stream), "copy psi");
+    std::vector<int> ngroups(n_hams);
+    size_t ecols = 0;
+    for (size_t k = 0; k < n_hams; ++k) ecols += 2 * group_pauli_sum(&hams[k]).size();
+    const int Pn = adj.n_pslots;
+    s->outbuf.reserve((ecols + n_hams * (size_t)Pn + 1) * sizeof(double));
+    double* d_out = static_cast<double*>(s->outbuf.p);
+    size_t col = 0;
+    for (size_t k = 0; k < n_hams; ++k) {
+      DevPauli dp = upload_pauli(s, &hams[k], s->pauli);
+      ngroups[k] = (int)dp.groups.size();
+      run_pauli(s, dp, P + k * one, L + k * one, bs, 1, d_out + col);
+      col += 2 * dp.groups.size();
+    }
+    run_adjoint(s, adj, up[1], P, L, bs, (int)n_hams, d_out + ecols);
+    double* host = static_cast<double*>(stage_acquire(s, (ecols + n_hams * (size_t)Pn + 1) * sizeof(double)));
+    hip_check(hipMemcpyAsync(host, d_out, (ecols + n_hams * (size_t)Pn) * sizeof(double), hipMemcpyDeviceToHost,
+                             s->stream),
+              "download");
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    col = 0;
+    for (size_t k = 0; k < n_hams; ++k) {
+      double e = 0.0;
+      for (int g = 0; g < ngroups[k]; ++g) e += host[col + 2 * g];
+      col += 2 * ngroups[k];
+      out_E[k] = e;
+      if (!n_params) continue;
+      double* gk = out_grad + k * n_params;
+      for (size_t q = 0; q < n_params; ++q) gk[q] = 0.0;
+      for (int q = 0; q < Pn; ++q) gk[adj.pslot_param[q]] += host[ecols + k * Pn + q];
     }
   });
 }

@@ -23,6 +23,11 @@ hipError_t launch_reduce_segments(const double* in, const int64_t* offs, const i
                                   double* out, int ncols, hipStream_t s);
 hipError_t launch_set_zero_multi(int dtype, void* const* ptrs, const int32_t* nq, const uint32_t* prefix, int n_jobs,
                                  uint32_t n_wg, hipStream_t s);
+// dst = (ar + i ai) src for one 2^n state; inner product partials (re: [0, blocks),
+// im: [blocks, 2 blocks)) of conj(a) b.
+hipError_t launch_scale_copy(int dtype, void* dst, const void* src, int n, double ar, double ai, hipStream_t s);
+unsigned inner_blocks(int n);
+hipError_t launch_inner_product(int dtype, const void* a, const void* b, int n, double* partials, hipStream_t s);
 hipError_t launch_gate1(int dtype, void* psi, int64_t bstride, int batch, int n, int t, uint64_t cmask,
                         const void* ctab, int64_t ctab_bstride, int mat, hipStream_t s);
 hipError_t launch_gate2(int dtype, void* psi, int64_t bstride, int batch, int n, int ta, int tb,

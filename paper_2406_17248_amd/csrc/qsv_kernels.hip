@@ -923,6 +923,44 @@ __global__ __launch_bounds__(256) void set_zero_multi(void* const* ptrs, const i
   }
 }
 
+// dst = alpha * src (complex alpha), one state.
+template <typename R>
+__global__ __launch_bounds__(256) void scale_copy(void* dst_, const void* src_, uint64_t N, double ar, double ai) {
+  using C = typename CT<R>::T;
+  C* dst = reinterpret_cast<C*>(dst_);
+  const C* src = reinterpret_cast<const C*>(src_);
+  for (uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x; x < N; x += (uint64_t)gridDim.x * 256) {
+    const C v = src[x];
+    C o;
+    o.x = (R)(ar * v.x - ai * v.y);
+    o.y = (R)(ar * v.y + ai * v.x);
+    dst[x] = o;
+  }
+}
+
+// partials[blk] = sum conj(a[x]) b[x] (re at 2 blk, im at 2 blk + 1), fp64.
+template <typename R>
+__global__ __launch_bounds__(256) void inner_product(const void* a_, const void* b_, uint64_t N, double* partials) {
+  using C = typename CT<R>::T;
+  __shared__ double red[2][4];
+  const C* a = reinterpret_cast<const C*>(a_);
+  const C* b = reinterpret_cast<const C*>(b_);
+  double re = 0.0, im = 0.0;
+  for (uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x; x < N; x += (uint64_t)gridDim.x * 256) {
+    const C u = a[x], v = b[x];
+    re += (double)u.x * v.x + (double)u.y * v.y;
+    im += (double)u.x * v.y - (double)u.y * v.x;
+  }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = re; red[1][threadIdx.x >> 6] = im; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    partials[gridDim.x + blockIdx.x] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Host launchers.
 // ------------------------------------------------------------------------------------------
@@ -1023,6 +1061,25 @@ hipError_t launch_set_zero_multi(int dtype, void* const* ptrs, const int32_t* nq
                                  uint32_t n_wg, hipStream_t s) {
   if (dtype == 0) set_zero_multi<float><<<n_wg, 256, 0, s>>>(ptrs, nq, prefix, n_jobs);
   else set_zero_multi<double><<<n_wg, 256, 0, s>>>(ptrs, nq, prefix, n_jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(int dtype, void* dst, const void* src, int n, double ar, double ai, hipStream_t s) {
+  const unsigned grid = stream_blocks(1ull << n);
+  if (dtype == 0) scale_copy<float><<<grid, 256, 0, s>>>(dst, src, 1ull << n, ar, ai);
+  else scale_copy<double><<<grid, 256, 0, s>>>(dst, src, 1ull << n, ar, ai);
+  return hipGetLastError();
+}
+
+unsigned inner_blocks(int n) {
+  const unsigned b = stream_blocks(1ull << n);
+  return b < 1024 ? b : 1024;
+}
+
+hipError_t launch_inner_product(int dtype, const void* a, const void* b, int n, double* partials, hipStream_t s) {
+  const unsigned grid = inner_blocks(n);
+  if (dtype == 0) inner_product<float><<<grid, 256, 0, s>>>(a, b, 1ull << n, partials);
+  else inner_product<double><<<grid, 256, 0, s>>>(a, b, 1ull << n, partials);
   return hipGetLastError();
 }
 

@@ -341,3 +341,46 @@ def test_brick_and_qaoa_workload_shapes():
     assert len(edges) == 36 and params.shape == (64, 16)
     assert sum(g["kind"] == "RZZ" for g in circ["gates"]) == 288
     assert sum(g["kind"] == "RX" for g in circ["gates"]) == 192
+
+
+# ------------------------------------------------------------------------------------
+# General form <phi| U_l^dag H U_r |psi>
+# ------------------------------------------------------------------------------------
+def test_general_expectation_printed_inner_product():
+    """Section 2.6: with H = I, U_r = RX(2.5), U_l = RY(1.5) on |00> the printed inner
+    product is 0.23071786267161518 - 0.6468646992187576j."""
+    ur = W.circuit(2, [_gate("RX", 0, angles=(2.5,))])
+    ul = W.circuit(2, [_gate("RY", 0, angles=(1.5,))])
+    E = O.expectation_general(ur, None, O.zero_state(2), ul, None, O.zero_state(2), [(1.0, ())])
+    assert abs(E - (0.23071786267161518 - 0.6468646992187576j)) < 1e-15
+
+
+def test_general_gradient_matches_finite_differences_and_real_case():
+    n = 4
+    kinds = ["RX", "RY", "RZ", "PS", "RZZ", "U3", "H", "RXX"]
+    cr = W.random_circuit(n, 20, 31, kinds=kinds, max_ctrls=1, n_params=4, param_fraction=0.9)
+    cl = W.random_circuit(n, 15, 32, kinds=kinds, max_ctrls=1, n_params=3, param_fraction=0.9)
+    rng = np.random.default_rng(33)
+    H = W.random_pauli_sum(n, 8, rng)
+    psi, phi = W.random_state(n, rng), W.random_state(n, rng)
+    pr, pl = rng.uniform(-2, 2, 4), rng.uniform(-2, 2, 3)
+    E, gr, gl = O.grad_general(cr, pr, psi, cl, pl, phi, H)
+    h = 1e-6
+    for i in range(4):
+        e = np.zeros(4)
+        e[i] = h
+        fd = (O.expectation_general(cr, pr + e, psi, cl, pl, phi, H) -
+              O.expectation_general(cr, pr - e, psi, cl, pl, phi, H)) / (2 * h)
+        assert abs(fd - gr[i]) < 1e-8
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = h
+        fd = (O.expectation_general(cr, pr, psi, cl, pl + e, phi, H) -
+              O.expectation_general(cr, pr, psi, cl, pl - e, phi, H)) / (2 * h)
+        assert abs(fd - gl[i]) < 1e-8
+    # same circuit and state on both sides: the real gradient is 2 Re of the right part
+    Er, gr_same, gl_same = O.grad_general(cr, pr, psi, cr, pr, psi, H)
+    _, g_real = O.grad_adjoint(cr, H, pr, psi)
+    assert abs(Er.imag) < 1e-12
+    assert np.max(np.abs(2 * gr_same.real - g_real)) < 1e-11
+    assert np.max(np.abs(gr_same + gl_same - g_real)) < 1e-11
