@@ -348,16 +348,16 @@ std::vector<Prim> lower_adjoint(const qsv_circuit* c) {
     const bool any_param = g.kind == QSV_GATE_U3 &&
                            (g.param_index[0] >= 0 || g.param_index[1] >= 0 || g.param_index[2] >= 0);
     if (any_param) {
-      // U3 = e^{i(phi+lam)/2} RZ(phi) RY(theta) RZ(lam); with controls the phase becomes
-      // exp(i (phi/2) Pi_c) exp(i (lam/2) Pi_c).  Forward order of the parts:
+      // U3 = e^{i(phi+lam)/2} RZ(phi) RY(theta) RZ(lam); the phase is exp(i (phi/2) Pi_c)
+      // exp(i (lam/2) Pi_c) with Pi_c the control projector (the identity without controls,
+      // where it still matters for the derivatives of <phi|U_l^dag H U_r|psi>, which is
+      // linear in U_r).  Forward order of the parts:
       struct Part { int type, recipe, slot, gen; double scale; };
       std::vector<Part> parts = {{P_DIAG1, M_RZ_ANGLE, 2, G_Z, 1.0},
                                  {P_DENSE1, M_RY_ANGLE, 0, G_Y, 1.0},
-                                 {P_DIAG1, M_RZ_ANGLE, 1, G_Z, 1.0}};
-      if (g.ctrl_mask) {
-        parts.push_back({P_DIAG1, M_CPHASE_HALF, 1, G_CPHASE, 0.5});
-        parts.push_back({P_DIAG1, M_CPHASE_HALF, 2, G_CPHASE, 0.5});
-      }
+                                 {P_DIAG1, M_RZ_ANGLE, 1, G_Z, 1.0},
+                                 {P_DIAG1, M_CPHASE_HALF, 1, G_CPHASE, 0.5},
+                                 {P_DIAG1, M_CPHASE_HALF, 2, G_CPHASE, 0.5}};
       for (int k = (int)parts.size() - 1; k >= 0; --k) {
         Prim p{};
         p.type = parts[k].type;

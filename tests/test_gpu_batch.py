@@ -53,7 +53,7 @@ def test_graph_replays_with_eager_work_between(Q):
     for rep in range(3):
         p = params + rng.uniform(-0.5, 0.5, params.size)
         E, g = Q.qsv_batch_expectation_and_grad(b, p)
-        Q.qsv_apply_circuit(s, W.random_circuit(12, 40, rep))
+        Q.qsv_apply_circuit(s, W.random_circuit(12, 40, rep), np.zeros(8))
         Q.qsv_state_synchronize(s)
         for i in (0, 5, len(circs) - 1):
             pi = p[b.offsets[i]:b.offsets[i + 1]]
