@@ -115,7 +115,7 @@ def main():
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the engine keeps a whole state on a single MI355X; "
-              "multi-GPU runs are not part of this build (use --gpus 1)", file=sys.stderr)
+              "it has no multi-GPU mode (use --gpus 1)", file=sys.stderr)
         return 2
 
     import torch
