@@ -614,6 +614,7 @@ struct PassEmitter {
   uint64_t T;
   int loc[64];
   std::vector<int32_t> op_param;  // gradient parameter of each op of the pass (-1 none)
+  int32_t cur_lr = 0;             // register-blocked passes: current local register mask
 
   int alloc(int count) {
     const int off = plan.ctab_size;
@@ -628,6 +629,22 @@ struct PassEmitter {
       gm &= gm - 1;
     }
     return lm;
+  }
+  // Split a diagonal entry's local condition into its thread-index part and the set of
+  // register slots that satisfy its register part, for the current register layout.
+  void slot_masks(DiagEntry& d) const {
+    const uint32_t lr = (uint32_t)cur_lr;
+    d.tmask = d.lcmask & ~lr;
+    const uint32_t rm = d.lcmask & lr;
+    int pos[32], np = 0;
+    for (int bit = 0; bit < 32; ++bit)
+      if (lr >> bit & 1) pos[np++] = bit;
+    d.kmask = 0;
+    for (int k = 0; k < (1 << kRegBits); ++k) {
+      uint32_t bits = 0;
+      for (int i = 0; i < np && i < kRegBits; ++i) bits |= (uint32_t)((k >> i) & 1) << pos[i];
+      if ((bits & rm) == rm) d.kmask |= 1u << k;
+    }
   }
   void push(const TileOp& op, int32_t param) {
     plan.ops.push_back(op);
@@ -749,6 +766,7 @@ struct PassEmitter {
         d.l1 = d.q1 >= 0 ? loc[d.q1] : -1;
         d.lcmask = local_mask(q.cmask & T);
         d.ocmask = q.cmask & ~T;
+        slot_masks(d);
         d.mat = -1;
         d.gen = -1;
         if (q.type != P_SIGN) {
@@ -856,17 +874,17 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
         if (cur < 0) {
           // first round: load straight into its layout when the coalescing bits stay thread bits
           cur = (has_dense && (lr & low_mask) == 0) ? lr : top;
-          dp.lr0 = cur;
+          dp.lr0 = em.cur_lr = cur;
         }
         if (has_dense && lr != cur) {
           em.remap(lr);
-          cur = lr;
+          em.cur_lr = cur = lr;
         }
         int reg_index[32];
         for (int bit = 0, ri2 = 0; bit < 32; ++bit) reg_index[bit] = (cur >> bit & 1) ? ri2++ : -1;
         em.emit(rounds[ri].prims, reg_index);
       }
-      if (cur < 0) dp.lr0 = cur = top;
+      if (cur < 0) dp.lr0 = em.cur_lr = cur = top;
       em.flush();
       if (cur & low_mask) em.remap(top);
     }

@@ -43,6 +43,17 @@ template <typename C> __device__ __forceinline__ double im_conj_mul(C w, C g) {
   return (double)w.x * (double)g.y - (double)w.y * (double)g.x;
 }
 
+// Negate v when f is 0x80000000 (f = 0: unchanged), by flipping the sign bits.
+__device__ __forceinline__ void flip_sign(float2& v, uint32_t f) {
+  v.x = __uint_as_float(__float_as_uint(v.x) ^ f);
+  v.y = __uint_as_float(__float_as_uint(v.y) ^ f);
+}
+__device__ __forceinline__ void flip_sign(double2& v, uint32_t f) {
+  const uint64_t g = (uint64_t)f << 32;
+  v.x = __longlong_as_double(__double_as_longlong(v.x) ^ g);
+  v.y = __longlong_as_double(__double_as_longlong(v.y) ^ g);
+}
+
 // Deposit the low bits of v into the set positions of mask (ascending).
 __device__ __forceinline__ uint64_t pdep64(uint64_t v, uint64_t mask) {
   uint64_t r = 0;
@@ -370,6 +381,19 @@ __device__ __forceinline__ void reg1_dispatch(int i, C* v, C* w, const int* jk, 
 
 __device__ __forceinline__ int insert_zero(int t, int p) { return ((t >> p) << (p + 1)) | (t & ((1 << p) - 1)); }
 
+// Sign-only diagonal entries in a register-blocked pass: bit k of the result is the
+// parity of the entries satisfied by register slot k, from the per-entry thread mask and
+// slot set (jt = the thread's local index with its register bits zero).
+__device__ __forceinline__ uint32_t sign_slots(const DiagEntry* d, int count, uint64_t base, uint32_t jt) {
+  uint32_t sm = 0;
+  for (int e = 0; e < count; ++e) {
+    const uint64_t ocm = ld(&d[e].ocmask);
+    const uint32_t tm = ld(&d[e].tmask);
+    if ((base & ocm) == ocm && (jt & tm) == tm) sm ^= ld(&d[e].kmask);
+  }
+  return sm;
+}
+
 template <typename R, int RB, int MAXM, bool ADJ>
 __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, const int b) {
   using C = typename CT<R>::T;
@@ -515,41 +539,30 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
       apply_staged(v);
       if (ADJ) apply_staged(w);
     } else if (on && active && type == OP_DIAG && !ld(&O->b)) {
-      // sign flips only (Z, CZ, multi-controlled Z): parity of the satisfied masks
-      const int first = ld(&O->first), count = ld(&O->count);
-      int sign[NR];
-#pragma unroll
-      for (int k = 0; k < NR; ++k) sign[k] = 0;
-      for (int e = 0; e < count; ++e) {
-        const DiagEntry* d = A.diag + first + e;
-        const uint64_t ocm = ld(&d->ocmask);
-        if ((base & ocm) != ocm) continue;
-        const uint32_t lcm = ld(&d->lcmask);
-#pragma unroll
-        for (int k = 0; k < NR; ++k) sign[k] ^= (int)(((uint32_t)jk[k] & lcm) == lcm);
-      }
+      // sign flips only (Z, CZ, multi-controlled Z): the parity of the satisfied entries,
+      // as one bit per register slot (slot 0 holds the thread's own local index)
+      const uint32_t sm = sign_slots(A.diag + ld(&O->first), ld(&O->count), base, (uint32_t)jk[0]);
 #pragma unroll
       for (int k = 0; k < NR; ++k) {
-        if (sign[k]) {
-          v[k].x = -v[k].x; v[k].y = -v[k].y;
-          if (ADJ) { w[k].x = -w[k].x; w[k].y = -w[k].y; }
-        }
+        const uint32_t f = (sm << (31 - k)) & 0x80000000u;
+        flip_sign(v[k], f);
+        if (ADJ) flip_sign(w[k], f);
       }
     } else if (on && active && type == OP_DIAG) {
       const int first = ld(&O->first), count = ld(&O->count);
       C ph[NR];
-      int sign[NR];
       double gw[NR];
 #pragma unroll
-      for (int k = 0; k < NR; ++k) { ph[k] = C{1, 0}; sign[k] = 0; gw[k] = 0.0; }
+      for (int k = 0; k < NR; ++k) { ph[k] = C{1, 0}; gw[k] = 0.0; }
+      uint32_t sm = 0;
       for (int e = 0; e < count; ++e) {
         const DiagEntry* d = A.diag + first + e;
         const uint64_t ocm = ld(&d->ocmask);
         if ((base & ocm) != ocm) continue;  // an outside control is 0 in this tile
         const uint32_t lcm = ld(&d->lcmask);
         if (ld(&d->kind) == DIAG_SIGN) {
-#pragma unroll
-          for (int k = 0; k < NR; ++k) sign[k] ^= (int)(((uint32_t)jk[k] & lcm) == lcm);
+          const uint32_t tm = ld(&d->tmask);
+          if (((uint32_t)jk[0] & tm) == tm) sm ^= ld(&d->kmask);
         } else {
           const int l0 = ld(&d->l0), l1 = ld(&d->l1), q0 = ld(&d->q0), q1 = ld(&d->q1);
           const int mat = ld(&d->mat);
@@ -566,7 +579,7 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
 #pragma unroll
       for (int k = 0; k < NR; ++k) {
         C p = ph[k];
-        if (sign[k]) { p.x = -p.x; p.y = -p.y; }
+        flip_sign(p, (sm << (31 - k)) & 0x80000000u);
         if (ADJ) {
           acc += gw[k] * im_conj_mul(w[k], v[k]);
           w[k] = cmul(w[k], p);

@@ -60,6 +60,11 @@ struct DiagEntry {
   int32_t  l0, l1;
   uint32_t lcmask;
   uint64_t ocmask;
+  // Register-blocked passes, for the register layout in force when the entry runs:
+  // tmask = the bits of lcmask that are thread-index bits; kmask bit k is set when
+  // register slot k has every register bit of lcmask set.  The local condition
+  // (j & lcmask) == lcmask then reads ((j_thread & tmask) == tmask) && (kmask >> k & 1).
+  uint32_t tmask, kmask;
 };
 
 // One edge of an OP_ZZ run: global qubits (u, v) and their local bits in the pass's tile
