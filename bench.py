@@ -4,14 +4,17 @@
 Workload (one step): a 30-qubit random brick circuit of depth 20 (a Haar-random 2x2
 unitary on every qubit each layer, then CZ on alternating neighbour pairs: 600 + 290
 gates) applied to |0...0>, then <sum_i Z_i>.  A step runs state init, every fused tile
-pass and the expectation pass; inputs (the state) are resident in HBM throughout.
+pass and the expectation pass; the state is resident in HBM throughout.
 
-Reported `value`: achieved HBM throughput of the whole step, i.e. the algorithmic bytes
-of every launch (each pass reads and writes the 2^30-amplitude state once; the
-expectation reads it once; init writes it once) divided by the step time.  Extra fields
-give gates/s, the roofline of the dominant kernel (fused tile pass) from per-launch HIP
-event timings taken inside the timed steps, the adjoint-vs-parameter-shift gradient
-throughput on the 24-qubit QAOA batch, and the CPU oracle timed on a bounded sample.
+Reported `value`: HBM throughput of the whole step, i.e. the bytes every launch moves by
+schedule (each fused pass reads and writes the 2^30-amplitude state once, the
+expectation reads it once, init writes it once) divided by the step time.  The fused
+passes carry ~40 gates each, so their arithmetic intensity (~14 flop per amplitude per
+gate) is above the vector ridge point and the dominant kernel's roofline is the vector
+ALU: `roofline` gives its algorithmic flop rate from per-launch HIP event timings taken
+inside the timed steps on the library's stream.  Extra fields: gates/s, the same step in
+the other precision, adjoint-vs-parameter-shift gradient throughput on the 24-qubit QAOA
+batch, and the CPU oracle timed on a bounded sample.
 """
 
 import argparse
@@ -25,7 +28,43 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Published MI355X vector peaks (256 CUs x 64 lanes x FMA x 2.4 GHz = 78.6 TFLOP/s; FP32
+# doubles that only with packed two-wide FP32 instructions, which this library's build
+# turns off, so 78.6 is also what complex64 code can reach).
+VALU_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}
+VALU_NONPACKED_TFLOPS = 78.6
+# A 2x2 complex gate: each output amplitude is two complex multiplies and one complex
+# add (6 + 6 + 2 flop).  Sign-only gates (CZ) count as zero flop.
+FLOP_PER_AMP_DENSE1 = 14
 METRIC = "state-vector HBM GB/s vs peak; adjoint grad evals/s vs parameter-shift"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_pass_brick30_traffic.txt")
+TRAFFIC_SOURCES = ["qsv_kernels.hip", "engine.cpp", "api.cpp"]
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2406_17248_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def committed_traffic(dtype):
+    """HBM bytes per fused-pass launch from the committed rocprofv3 counter summary, or
+    None when it is missing or the kernel, planner or launch sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("sources_sha256") != sources_digest():
+        return None
+    try:
+        return float(kv[f"{dtype}_hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline_sample(n, depth, seconds):
@@ -94,6 +133,81 @@ def qaoa_leg(Q, dtype, ps_sets):
             "max_grad_diff_over_S": agree, "param_shift_sets": ps_sets}
 
 
+def brick_leg(Q, torch, circ, H, n, dtype, steps, warmup, tile, with_copy):
+    """Time `steps` brick steps in one precision; per-launch times come from HIP events the
+    library records on its stream around every launch while profiling is on."""
+    n_gates = len(circ["gates"])
+    n_dense = sum(1 for g in circ["gates"] if g["kind"] == "MAT1")
+    c, h = Q.Circuit(circ), Q.PauliSum(H)
+    s = Q.qsv_state_create(n, dtype)
+    if tile is not None:
+        Q.qsv_state_set_option(s, Q.OPT_TILE_QUBITS, tile)
+
+    def step():
+        Q.qsv_state_reset(s)
+        Q.qsv_apply_circuit(s, c)
+        return Q.qsv_expectation(s, h).real
+
+    log(f"brick n={n} dtype={dtype}: {warmup} warmup step(s)")
+    for _ in range(warmup):
+        step()
+    Q.qsv_state_set_option(s, Q.OPT_PROFILE, 1)
+    for k in range(5):
+        Q.qsv_profile_read(s, k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    prof = {k: Q.qsv_profile_read(s, k) for k in range(5)}
+    log(f"timed {steps} step(s): {dt * 1e3:.2f} ms/step")
+    if with_copy:
+        # plain copy kernel of known size (reads and writes the state once), for the
+        # calibration of hardware byte counters
+        d = Q.qsv_state_create(n, dtype)
+        Q.qsv_state_copy(d, s)
+        Q.qsv_state_synchronize(d)
+        log(f"copy calibration: {(2 ** n) * (8 if dtype == 'c64' else 16) * 2 / 1e9:.3f} GB moved")
+        del d
+    Q.qsv_state_set_option(s, Q.OPT_PROFILE, 0)
+    del s
+    torch.cuda.empty_cache()
+
+    total_bytes = sum(b for (_, _, b) in prof.values()) / steps
+    fused = bool(prof[Q.K_TILE_FORWARD][1])
+    dom = Q.K_TILE_FORWARD if fused else Q.K_GATE_STREAM
+    ms, launches, b = prof[dom]
+    launches = max(launches, 1)
+    avg_s = ms / launches / 1e3
+    bytes_per_launch = b / launches
+    hbm_gbs = bytes_per_launch / avg_s / 1e9
+    flops_per_launch = n_dense * FLOP_PER_AMP_DENSE1 * float(2 ** n) / (launches / steps)
+    achieved = flops_per_launch / avg_s / 1e12
+    peak = VALU_PEAK_TFLOPS[dtype]
+    traffic = committed_traffic(dtype) if fused else None
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": traffic,
+                "kernel": "tile_pass_rb (fused forward pass)" if fused else "gate1/gate2/diag_stream",
+                "launches_per_step": launches / steps, "avg_launch_ms": avg_s * 1e3,
+                "algorithmic_flop_per_launch": flops_per_launch,
+                "algorithmic_bytes_per_launch": bytes_per_launch,
+                "hbm_GBs": hbm_gbs, "hbm_frac": hbm_gbs / HBM_PEAK_GBS,
+                "frac_of_nonpacked_peak": achieved / VALU_NONPACKED_TFLOPS}
+    kernel_ms = {name: prof[k][0] / steps for name, k in
+                 (("tile_forward", Q.K_TILE_FORWARD), ("pauli", Q.K_PAULI), ("gate_stream", Q.K_GATE_STREAM),
+                  ("other", Q.K_OTHER))}
+    value = total_bytes / dt / 1e9
+    # the same circuit gate by gate (one read + write of the state per dense gate, a quarter
+    # of it per CZ) at this step time: how far fusion moves past the unfused HBM floor
+    state = float(2 ** n) * (8 if dtype == "c64" else 16)
+    unfused = n_dense * 2 * state + (n_gates - n_dense) * 2 * state / 4 + state
+    return {"value": value, "ms_per_step": dt * 1e3, "gates": n_gates, "gates_per_s": n_gates / dt,
+            "expectation": e, "kernel_ms_per_step": kernel_ms, "roofline": roofline,
+            "hbm_frac_of_peak": value / HBM_PEAK_GBS,
+            "unfused_equivalent_GBs": unfused / dt / 1e9, "state_bytes": int(state)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +219,9 @@ def main():
     ap.add_argument("--tile", type=int, default=None, help="tile qubits (0: unfused per-gate kernels)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-qaoa", action="store_true")
+    ap.add_argument("--no-other-dtype", action="store_true", help="skip the second precision")
+    ap.add_argument("--with-copy", action="store_true",
+                    help="after the timed steps, run one plain state copy (counter calibration)")
     ap.add_argument("--ps-sets", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
@@ -127,64 +244,32 @@ def main():
     torch.cuda.set_device(0)
     n, depth = args.n_qubits, args.depth
     circ, H = W.brick_workload(n, depth)
-    n_gates = len(circ["gates"])
-    c, h = Q.Circuit(circ), Q.PauliSum(H)
-    s = Q.qsv_state_create(n, args.dtype)
-    if args.tile is not None:
-        Q.qsv_state_set_option(s, Q.OPT_TILE_QUBITS, args.tile)
+    main_leg = brick_leg(Q, torch, circ, H, n, args.dtype, args.steps, args.warmup, args.tile, args.with_copy)
 
-    def step():
-        Q.qsv_state_reset(s)
-        Q.qsv_apply_circuit(s, c)
-        return Q.qsv_expectation(s, h).real
-
-    log(f"brick n={n} depth={depth} dtype={args.dtype}: warmup")
-    for _ in range(args.warmup):
-        step()
-    log("warmup done; timing")
-    Q.qsv_state_set_option(s, Q.OPT_PROFILE, 1)
-    for k in range(5):
-        Q.qsv_profile_read(s, k)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        e = step()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    prof = {k: Q.qsv_profile_read(s, k) for k in range(5)}
-    log(f"timed {args.steps} steps: {dt * 1e3:.2f} ms/step")
-    Q.qsv_state_set_option(s, Q.OPT_PROFILE, 0)
-
-    total_bytes = sum(b for (_, _, b) in prof.values()) / args.steps
-    value = total_bytes / dt / 1e9
-    dom = Q.K_TILE_FORWARD if prof[Q.K_TILE_FORWARD][1] else Q.K_GATE_STREAM
-    ms, launches, b = prof[dom]
-    avg_ms = ms / max(launches, 1)
-    achieved = (b / max(launches, 1)) / (avg_ms / 1e3) / 1e9 if launches else 0.0
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "tile_pass (fused forward)" if dom == Q.K_TILE_FORWARD else "gate1/gate2/diag_stream",
-                "launches_per_step": launches / args.steps, "avg_launch_ms": avg_ms,
-                "algorithmic_bytes_per_launch": b / max(launches, 1)}
-    kernel_ms = {name: prof[k][0] / args.steps for name, k in
-                 (("tile_forward", Q.K_TILE_FORWARD), ("pauli", Q.K_PAULI), ("gate_stream", Q.K_GATE_STREAM),
-                  ("other", Q.K_OTHER))}
-    del s
-    torch.cuda.empty_cache()
-
-    out = {"metric": METRIC, "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32" if args.dtype == "c64" else "f64", "data": "synthetic",
+    out = {"metric": METRIC, "value": main_leg["value"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": main_leg["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.dtype == "c64" else "f64",
+           "data": "synthetic",
            "config": {"workload": f"brick{n}_depth{depth}_sumZ", "n_qubits": n, "depth": depth,
-                      "gates": n_gates, "amplitude_type": "complex64" if args.dtype == "c64" else "complex128",
-                      "state_bytes": (2 ** n) * (8 if args.dtype == "c64" else 16), "parallelism": "single-gpu"},
-           "gates_per_s": n_gates / dt, "expectation": e, "hbm_frac_of_peak": value / HBM_PEAK_GBS,
-           "kernel_ms_per_step": kernel_ms, "roofline": roofline}
+                      "gates": main_leg["gates"],
+                      "amplitude_type": "complex64" if args.dtype == "c64" else "complex128",
+                      "state_bytes": main_leg["state_bytes"], "parallelism": "single-gpu"}}
+    for k in ("gates_per_s", "expectation", "hbm_frac_of_peak", "unfused_equivalent_GBs", "kernel_ms_per_step",
+              "roofline"):
+        out[k] = main_leg[k]
+    other = "c64" if args.dtype == "c128" else "c128"
+    if not args.no_other_dtype:
+        leg = brick_leg(Q, torch, circ, H, n, other, args.steps, args.warmup, args.tile, False)
+        out["other_dtype"] = {"dtype": other, **{k: leg[k] for k in ("value", "ms_per_step", "gates_per_s",
+                                                                   "expectation", "unfused_equivalent_GBs",
+                                                                   "roofline")}}
     if not args.no_qaoa:
-        try:
-            out["qaoa"] = qaoa_leg(Q, args.dtype, args.ps_sets)
-        except Exception as ex:  # report, do not hide, a failure of the secondary leg
-            out["qaoa"] = {"error": repr(ex)}
+        out["qaoa"] = []
+        for dt_ in ([args.dtype] if args.no_other_dtype else [args.dtype, other]):
+            try:
+                out["qaoa"].append(qaoa_leg(Q, dt_, args.ps_sets))
+            except Exception as ex:  # report, do not hide, a failure of the secondary leg
+                out["qaoa"].append({"dtype": dt_, "error": repr(ex)})
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, single thread)")
         out["cpu_baseline"] = run_cpu_baseline(n, depth, args.cpu_seconds)

@@ -143,7 +143,9 @@ int qsv_state_reset(qsv_state* s);
 int qsv_state_set(qsv_state* s, const void* host_amps, size_t n_amps);
 /* Copy the state to n_amps = 2^n host amplitudes of its dtype (get_qs). */
 int qsv_state_get(qsv_state* s, void* host_amps, size_t n_amps);
-/* Copy the amplitudes of src into dst (same n and dtype). */
+/* Copy the amplitudes of src into dst (same n and dtype) with one plain copy kernel on
+   dst's stream (reads and writes 2^n amplitudes once each); work on src's stream, if it
+   differs, must be ordered before the call by the caller. */
 int qsv_state_copy(qsv_state* dst, const qsv_state* src);
 
 /* Execution options (integers).  Defaults are chosen per dtype and n. */

@@ -590,9 +590,9 @@ int qsv_state_copy(qsv_state* dst, const qsv_state* src) {
     if (dst->n != src->n) fail(QSV_EINVAL, "n_qubits mismatch");
     if (dst == src) return;
     set_device(dst);
-    hip_check(hipMemcpyAsync(dst->psi, src->psi, dst->namps() * dst->amp_bytes(), hipMemcpyDeviceToDevice,
-                             dst->stream),
-              "copy state");
+    timed(dst, QSV_K_OTHER, 2.0 * (double)dst->namps() * (double)dst->amp_bytes(),
+          [&] { return launch_broadcast_state(dst->dtype, dst->psi, 0, 1, src->psi, dst->n, dst->stream); },
+          "copy state");
   });
 }
 

@@ -335,23 +335,53 @@ __device__ __forceinline__ int swz(int j) {
   return j ^ (f & ((1 << S) - 1));
 }
 
+template <typename C> __device__ __forceinline__ C csel(bool c, C a, C b) {
+  C r;
+  r.x = c ? a.x : b.x;
+  r.y = c ? a.y : b.y;
+  return r;
+}
+
+// 2x2 gate on register bit I.  Gates without local controls (the common case, a
+// wave-uniform test) run straight-line; controlled ones compute every pair and keep the
+// old values by select where a control bit is 0, so no lane-divergent branch is formed.
 template <int I, int NR, bool ADJ, typename C>
 __device__ __forceinline__ void reg1(C* v, C* w, const int* jk, uint32_t lm, const C* U, bool grad,
                                      const C* G, double& acc) {
+  if (lm == 0) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      if (k & (1 << I)) continue;
+      const int k1 = k | (1 << I);
+      const C a0 = v[k], a1 = v[k1];
+      if (ADJ) {
+        const C b0 = w[k], b1 = w[k1];
+        if (grad) acc += im_conj_mul(b0, cdot2(G[0], a0, G[1], a1)) + im_conj_mul(b1, cdot2(G[2], a0, G[3], a1));
+        w[k] = cdot2(U[0], b0, U[1], b1);
+        w[k1] = cdot2(U[2], b0, U[3], b1);
+      }
+      v[k] = cdot2(U[0], a0, U[1], a1);
+      v[k1] = cdot2(U[2], a0, U[3], a1);
+    }
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
     if (k & (1 << I)) continue;
     const int k1 = k | (1 << I);
-    if (((uint32_t)jk[k] & lm) != lm) continue;
+    const bool ok = ((uint32_t)jk[k] & lm) == lm;
     const C a0 = v[k], a1 = v[k1];
     if (ADJ) {
       const C b0 = w[k], b1 = w[k1];
-      if (grad) acc += im_conj_mul(b0, cdot2(G[0], a0, G[1], a1)) + im_conj_mul(b1, cdot2(G[2], a0, G[3], a1));
-      w[k] = cdot2(U[0], b0, U[1], b1);
-      w[k1] = cdot2(U[2], b0, U[3], b1);
+      if (grad) {
+        const double g = im_conj_mul(b0, cdot2(G[0], a0, G[1], a1)) + im_conj_mul(b1, cdot2(G[2], a0, G[3], a1));
+        acc += ok ? g : 0.0;
+      }
+      w[k] = csel(ok, cdot2(U[0], b0, U[1], b1), b0);
+      w[k1] = csel(ok, cdot2(U[2], b0, U[3], b1), b1);
     }
-    v[k] = cdot2(U[0], a0, U[1], a1);
-    v[k1] = cdot2(U[2], a0, U[3], a1);
+    v[k] = csel(ok, cdot2(U[0], a0, U[1], a1), a0);
+    v[k1] = csel(ok, cdot2(U[2], a0, U[3], a1), a1);
   }
 }
 
