@@ -133,6 +133,76 @@ def qaoa_leg(Q, dtype, ps_sets):
             "max_grad_diff_over_S": agree, "param_shift_sets": ps_sets}
 
 
+def max_cut(edges, n_nodes):
+    """Brute-force maximum cut of a small graph (all 2^n bipartitions)."""
+    import numpy as np
+    x = np.arange(1 << n_nodes, dtype=np.int64)
+    cut = np.zeros(1 << n_nodes, dtype=np.int64)
+    for (u, v) in edges:
+        cut += ((x >> u) ^ (x >> v)) & 1
+    return int(cut.max())
+
+
+def warmstart_leg(n_train, n_test, epochs, restarts, chunk=2048, opt_steps=150):
+    """Learned warm start at full size: labels are angles the simulator optimized (Adam on
+    adjoint gradients from the linear ramp and from `restarts` random starts, best kept),
+    the network is trained on them by the library's kernels, and 1k held-out graphs are
+    started from the ramp and from the network's angles; the simulator reports the cut
+    reached and the optimizer steps needed to reach the ramp run's final cut."""
+    import numpy as np
+
+    import paper_2406_17248_amd as Q
+    import workloads as W
+    from paper_2406_17248_amd import warmstart as WS
+    ramp = W.linear_ramp()
+    p2 = ramp.size
+    t0 = time.perf_counter()
+    train_g = W.warmstart_graphs(n_train, 11)
+    test_g = W.warmstart_graphs(n_test, 12)
+    rng = np.random.default_rng(5)
+    labels = np.zeros((n_train, p2))
+    sim_calls = 0
+    for s in range(0, n_train, chunk):
+        graphs = train_g[s:s + chunk]
+        qb = WS.QaoaBatch(graphs, W.qaoa_circuit, W.maxcut_hamiltonian)
+        best_x, best_c, _ = WS.optimize(qb, np.tile(ramp, (len(graphs), 1)), steps=opt_steps)
+        for _ in range(restarts):
+            init = np.concatenate([rng.uniform(-np.pi / 2, 0, (len(graphs), p2 // 2)),
+                                   rng.uniform(0, np.pi, (len(graphs), p2 // 2))], axis=1)
+            x, c, _ = WS.optimize(qb, init, steps=opt_steps)
+            better = c > best_c
+            best_x[better], best_c[better] = x[better], c[better]
+        sim_calls += (1 + restarts) * (opt_steps + 1)
+        labels[s:s + len(graphs)] = best_x
+        log(f"warm start labels {s + len(graphs)}/{n_train}")
+    t_labels = time.perf_counter() - t0
+    masks = np.stack([WS.adjacency_masks(e) for e in train_g])
+    net = Q.Mpnn(WS.init_params(1))
+    t1 = time.perf_counter()
+    losses = WS.train(net, masks, labels, ramp, epochs=epochs, batch_size=256, lr=3e-3)
+    t_train = time.perf_counter() - t1
+    log(f"trained {epochs} epochs: loss {losses[:10].mean():.4f} -> {losses[-10:].mean():.4f}")
+    qb = WS.QaoaBatch(test_g, W.qaoa_circuit, W.maxcut_hamiltonian)
+    tmasks = np.stack([WS.adjacency_masks(e) for e in test_g])
+    init_r = np.tile(ramp, (n_test, 1))
+    init_n = net.predict(tmasks, ramp)
+    mc = np.array([max_cut(e, 16) for e in test_g], dtype=np.float64)
+    c0_r, _ = qb.cut_and_grad(init_r)
+    c0_n, _ = qb.cut_and_grad(init_n)
+    _, cf_r, _ = WS.optimize(qb, init_r, steps=opt_steps)
+    target = cf_r - 1e-3 * qb.n_edges
+    _, _, hit_r = WS.optimize(qb, init_r, steps=opt_steps, target=target)
+    _, cf_n, hit_n = WS.optimize(qb, init_n, steps=opt_steps, target=target)
+    return {"workload": f"qaoa16_p6_warmstart_{n_train}train_{n_test}test", "dtype": "c64 simulator, fp32 network",
+            "label_restarts": 1 + restarts, "optimizer_steps": opt_steps, "epochs": epochs,
+            "train_loss_first": float(losses[:10].mean()), "train_loss_last": float(losses[-10:].mean()),
+            "approx_ratio_init_ramp": float((c0_r / mc).mean()), "approx_ratio_init_net": float((c0_n / mc).mean()),
+            "approx_ratio_opt_ramp": float((cf_r / mc).mean()), "approx_ratio_opt_net": float((cf_n / mc).mean()),
+            "steps_to_ramp_final_cut_ramp": float(hit_r.mean()), "steps_to_ramp_final_cut_net": float(hit_n.mean()),
+            "steps_saved_frac": float(1.0 - hit_n.mean() / max(hit_r.mean(), 1e-9)),
+            "label_simulator_batch_calls": sim_calls, "seconds_labels": t_labels, "seconds_train": t_train}
+
+
 def brick_leg(Q, torch, circ, H, n, dtype, steps, warmup, tile, with_copy):
     """Time `steps` brick steps in one precision; per-launch times come from HIP events the
     library records on its stream around every launch while profiling is on."""
@@ -225,6 +295,12 @@ def main():
     ap.add_argument("--ps-sets", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--warmstart", action="store_true",
+                    help="run only the learned warm-start experiment (20k train / 1k test graphs)")
+    ap.add_argument("--ws-train", type=int, default=20000)
+    ap.add_argument("--ws-test", type=int, default=1000)
+    ap.add_argument("--ws-epochs", type=int, default=40)
+    ap.add_argument("--ws-restarts", type=int, default=2)
     args = ap.parse_args()
 
     if args.cpu_baseline_only:
@@ -242,6 +318,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.warmstart:
+        print(json.dumps(warmstart_leg(args.ws_train, args.ws_test, args.ws_epochs, args.ws_restarts)), flush=True)
+        return 0
     n, depth = args.n_qubits, args.depth
     circ, H = W.brick_workload(n, depth)
     main_leg = brick_leg(Q, torch, circ, H, n, args.dtype, args.steps, args.warmup, args.tile, args.with_copy)
