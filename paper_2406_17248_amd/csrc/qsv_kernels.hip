@@ -76,6 +76,17 @@ __device__ __forceinline__ double wave_sum(double v) {
 // through the scalar cache instead of vector memory instructions.
 #define QSV_CONST __attribute__((address_space(4)))
 template <typename T> __device__ __forceinline__ T ld(const T* p) { return *(const QSV_CONST T*)p; }
+// A whole record through the scalar path, dword by dword (the loads merge into wide
+// scalar loads).
+template <typename T> __device__ __forceinline__ T ld_record(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "record size must be a multiple of 4 bytes");
+  T r;
+  uint32_t* d = reinterpret_cast<uint32_t*>(&r);
+  const QSV_CONST uint32_t* q = (const QSV_CONST uint32_t*)(const void*)p;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = q[i];
+  return r;
+}
 template <typename C> __device__ __forceinline__ C ldc(const C* p) {
   using R = decltype(p->x);
   const QSV_CONST R* q = (const QSV_CONST R*)p;
@@ -414,12 +425,32 @@ __device__ __forceinline__ int insert_zero(int t, int p) { return ((t >> p) << (
 // Sign-only diagonal entries in a register-blocked pass: bit k of the result is the
 // parity of the entries satisfied by register slot k, from the per-entry thread mask and
 // slot set (jt = the thread's local index with its register bits zero).
+// The three fields are contiguous (16 bytes), so each entry is one scalar load, and four
+// entries are requested before the first is used.
+struct SignFields {
+  uint64_t ocmask;
+  uint32_t tmask, kmask;
+};
+static_assert(offsetof(DiagEntry, tmask) == offsetof(DiagEntry, ocmask) + 8 &&
+                  offsetof(DiagEntry, kmask) == offsetof(DiagEntry, ocmask) + 12,
+              "sign fields must be contiguous");
+__device__ __forceinline__ SignFields sign_fields(const DiagEntry* d) {
+  return ld_record(reinterpret_cast<const SignFields*>(&d->ocmask));
+}
 __device__ __forceinline__ uint32_t sign_slots(const DiagEntry* d, int count, uint64_t base, uint32_t jt) {
   uint32_t sm = 0;
-  for (int e = 0; e < count; ++e) {
-    const uint64_t ocm = ld(&d[e].ocmask);
-    const uint32_t tm = ld(&d[e].tmask);
-    if ((base & ocm) == ocm && (jt & tm) == tm) sm ^= ld(&d[e].kmask);
+  int e = 0;
+  for (; e + 4 <= count; e += 4) {
+    SignFields f[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f[i] = sign_fields(d + e + i);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if ((base & f[i].ocmask) == f[i].ocmask && (jt & f[i].tmask) == f[i].tmask) sm ^= f[i].kmask;
+  }
+  for (; e < count; ++e) {
+    const SignFields f = sign_fields(d + e);
+    if ((base & f.ocmask) == f.ocmask && (jt & f.tmask) == f.tmask) sm ^= f.kmask;
   }
   return sm;
 }
