@@ -220,6 +220,8 @@ void upload_plans(qsv_state* s, const UploadReq* reqs, int n_req, Uploaded* out)
 
 hipError_t launch_pass(const qsv_state* s, const DevPass& dp, PassArgs A, int batch, bool adj) {
   A.lr0 = dp.lr0;
+  A.win_lo = dp.win_lo;
+  A.win_n = dp.rb ? dp.win_n : 0;
   const uint64_t tiles = 1ull << (s->n - dp.m);
   A.n_tiles = (int64_t)tiles;
   if (dp.rb) return launch_tile_pass_rb(s->dtype, adj, dp.maxm, A, tiles, batch, s->stream);

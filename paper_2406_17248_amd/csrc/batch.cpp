@@ -42,6 +42,7 @@ struct Round {
   std::vector<PassArgs> items;
   std::vector<uint32_t> prefix;  // n_items + 1
   int maxm = 9;
+  int max_win = 0;                       // largest ctab window of the items (LDS entries)
   size_t items_off = 0, prefix_off = 0;  // byte offsets in the static device table
 };
 
@@ -248,6 +249,8 @@ void build(qsv_batch* b) {
         A.n_qubits = b->circ[i].n;
         A.m = dp.m;
         A.lr0 = dp.lr0;
+        A.win_lo = dp.win_lo;
+        A.win_n = dp.win_n;
         A.n_tiles = 1ll << (b->circ[i].n - dp.m);
         A.n_pslots = adjoint ? p.n_pslots : 0;
         // pointer fields hold offsets for now: fixed up once the device base is known
@@ -261,6 +264,7 @@ void build(qsv_batch* b) {
         rd.items.push_back(A);
         rd.prefix.push_back(rd.prefix.back() + (uint32_t)A.n_tiles);
         rd.maxm = std::max(rd.maxm, dp.maxm);
+        rd.max_win = std::max(rd.max_win, dp.win_n);
       }
       rd.items_off = align_up(st.size(), 256);
       st.resize(rd.items_off + rd.items.size() * sizeof(PassArgs));
@@ -322,7 +326,7 @@ void build(qsv_batch* b) {
     if (e != hipSuccess) break;
     e = launch_tile_pass_rb_multi(dt, false, rd.maxm, reinterpret_cast<const PassArgs*>(sbase + rd.items_off),
                                   reinterpret_cast<const uint32_t*>(sbase + rd.prefix_off), (int)rd.items.size(),
-                                  rd.prefix.back(), b->stream);
+                                  rd.prefix.back(), rd.max_win, b->stream);
   }
   if (e == hipSuccess)
     e = launch_pauli_apply_multi(dt, reinterpret_cast<const PauliJob*>(sbase + p_jobs),
@@ -331,7 +335,7 @@ void build(qsv_batch* b) {
     if (e != hipSuccess) break;
     e = launch_tile_pass_rb_multi(dt, true, rd.maxm, reinterpret_cast<const PassArgs*>(sbase + rd.items_off),
                                   reinterpret_cast<const uint32_t*>(sbase + rd.prefix_off), (int)rd.items.size(),
-                                  rd.prefix.back(), b->stream);
+                                  rd.prefix.back(), rd.max_win, b->stream);
   }
   if (e == hipSuccess)
     e = launch_reduce_segments(part, reinterpret_cast<const int64_t*>(sbase + seg_offs),

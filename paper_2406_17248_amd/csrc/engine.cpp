@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <sstream>
@@ -646,6 +647,23 @@ struct PassEmitter {
       if ((bits & rm) == rm) d.kmask |= 1u << k;
     }
   }
+  // A ZZ edge with its thread-bit mask, outside-bit mask and (in pad, until the run is
+  // sorted) its register class for the current register layout.
+  ZZEdge edge_in_layout(int u, int v) const {
+    ZZEdge ed{u, v, loc[u], loc[v], 0, 0, 0};
+    const uint32_t lr = (uint32_t)cur_lr;
+    for (int q : {u, v}) {
+      const int l = loc[q];
+      if (l < 0) {
+        ed.omask |= 1ull << q;
+      } else if (lr >> l & 1) {
+        ed.pad ^= 1u << __builtin_popcount(lr & ((1u << l) - 1));  // register index of bit l
+      } else {
+        ed.tmask |= 1u << l;
+      }
+    }
+    return ed;
+  }
   void push(const TileOp& op, int32_t param) {
     plan.ops.push_back(op);
     op_param.push_back(param);
@@ -726,10 +744,24 @@ struct PassEmitter {
           op.type = OP_ZZ;
           op.first = (int32_t)plan.edges.size();
           op.count = (int32_t)(e - k);
+          std::vector<ZZEdge> run;
           for (size_t r = k; r < e; ++r) {
             const int u = plan.prims[seq[r]].q0, v = plan.prims[seq[r]].q1;
-            plan.edges.push_back(ZZEdge{u, v, loc[u], loc[v]});
+            run.push_back(edge_in_layout(u, v));
           }
+          if (cur_lr != 0) {
+            // register-blocked: edges grouped by class, class sizes packed in a and b
+            std::stable_sort(run.begin(), run.end(),
+                             [](const ZZEdge& x, const ZZEdge& y) { return x.pad < y.pad; });
+            uint32_t n_cls[8] = {0};
+            for (const ZZEdge& ed : run) n_cls[ed.pad]++;
+            for (int c = 0; c < 8; ++c)
+              if (n_cls[c] > 255) fail(QSV_EINVAL, "internal: too many edges in one ZZ class");
+            op.a = (int32_t)(n_cls[0] | n_cls[1] << 8 | n_cls[2] << 16 | n_cls[3] << 24);
+            op.b = (int32_t)(n_cls[4] | n_cls[5] << 8 | n_cls[6] << 16 | n_cls[7] << 24);
+          }
+          for (ZZEdge& ed : run) ed.pad = 0;
+          plan.edges.insert(plan.edges.end(), run.begin(), run.end());
           op.mat = alloc(op.count + 1);
           plan.fills.push_back({F_ZZ_PHASES, seq[k], op.count, op.mat});
           if (adjoint && p.gen != G_NONE) {
@@ -909,6 +941,34 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
       plan.n_pslots += dp.pslot_count;
     }
     dp.op_count = (int32_t)plan.ops.size() - dp.op_first;
+    if (rb) {
+      // ctab window of the per-lane lookups (ZZ phase / generator tables, phase entries)
+      int64_t lo = INT64_MAX, hi = INT64_MIN;
+      auto cover = [&](int64_t off, int64_t n) {
+        if (off < 0) return;
+        lo = std::min(lo, off);
+        hi = std::max(hi, off + n);
+      };
+      for (int i = 0; i < dp.op_count; ++i) {
+        const TileOp& o = plan.ops[dp.op_first + i];
+        if (o.type == OP_ZZ) {
+          cover(o.mat, o.count + 1);
+          cover(o.gen, o.count + 1);
+        } else if (o.type == OP_DIAG && o.b) {
+          for (int e = 0; e < o.count; ++e) {
+            const DiagEntry& d = plan.diag[o.first + e];
+            if (d.kind != DIAG_PHASE) continue;
+            const int n = d.q1 >= 0 ? 4 : 2;
+            cover(d.mat, n);
+            cover(d.gen, n);
+          }
+        }
+      }
+      if (hi > lo && hi - lo <= kMaxWindow) {
+        dp.win_lo = (int32_t)lo;
+        dp.win_n = (int32_t)(hi - lo);
+      }
+    }
     plan.passes.push_back(dp);
   }
   return plan;

@@ -86,6 +86,7 @@ struct DevPass {
   int32_t  lr0;        // register-blocked: local register mask at load time
   int32_t  op_first, op_count;
   int32_t  pslot_first, pslot_count;
+  int32_t  win_lo, win_n;  // register-blocked: ctab window of the pass's per-lane lookups
 };
 
 // A fully planned execution (forward or adjoint reverse sweep) of one circuit structure.

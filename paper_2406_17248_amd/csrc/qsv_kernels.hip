@@ -422,6 +422,9 @@ __device__ __forceinline__ void reg1_dispatch(int i, C* v, C* w, const int* jk, 
 
 __device__ __forceinline__ int insert_zero(int t, int p) { return ((t >> p) << (p + 1)) | (t & ((1 << p) - 1)); }
 
+// Dynamic LDS of the register-blocked passes (ctab window), sized per launch.
+extern __shared__ __align__(16) unsigned char qsv_dyn_lds[];
+
 // Sign-only diagonal entries in a register-blocked pass: bit k of the result is the
 // parity of the entries satisfied by register slot k, from the per-entry thread mask and
 // slot set (jt = the thread's local index with its register bits zero).
@@ -498,7 +501,14 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
     dep_lo[i] = pdep64((uint64_t)i, TM);
     dep_hi[i] = pdep64((uint64_t)i << 7, TM);
   }
+  // The pass's per-lane table lookups (ZZ phases and generator weights, phase entries) read
+  // a copy of their ctab window in dynamic LDS.
+  C* win = reinterpret_cast<C*>(qsv_dyn_lds);
+  const int win_n = A.win_n;
+  const int64_t win_lo = A.win_lo;
+  for (int i = tid; i < win_n; i += NT) win[i] = T[win_lo + i];
   __syncthreads();
+  auto tab = [&](int off) -> C { return win_n ? win[off - win_lo] : ldc(T + off); };
   auto globals = [&](uint64_t* xo) {
 #pragma unroll
     for (int k = 0; k < NR; ++k) xo[k] = base | dep_lo[jk[k] & 127] | dep_hi[jk[k] >> 7];
@@ -632,8 +642,8 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
           for (int k = 0; k < NR; ++k) {
             if (((uint32_t)jk[k] & lcm) != lcm) continue;
             const int idx = gbit(jk[k], l0, q0) | (q1 >= 0 ? gbit(jk[k], l1, q1) << 1 : 0);
-            ph[k] = cmul(ph[k], ldc(T + mat + idx));
-            if (ADJ && dg >= 0) gw[k] += (double)ldc(T + dg + idx).x;
+            ph[k] = cmul(ph[k], tab(mat + idx));
+            if (ADJ && dg >= 0) gw[k] += (double)tab(dg + idx).x;
           }
         }
       }
@@ -648,21 +658,37 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
         v[k] = cmul(v[k], p);
       }
     } else if (on && active && type == OP_ZZ) {
-      const int first = ld(&O->first), count = ld(&O->count), mat = ld(&O->mat), gen = ld(&O->gen);
+      // c(x) = number of edges whose endpoints differ.  Edges come grouped by register
+      // class c; an edge of class c differs in slot k iff its thread/outside parity
+      // differs from the parity of (k & c), so with a_c = the class's edges whose
+      // thread/outside parity is odd, c(slot k) = sum_c a_c + sum_{c: k & c odd} (n_c - 2 a_c).
+      const int first = ld(&O->first), mat = ld(&O->mat), gen = ld(&O->gen);
+      const uint32_t ca = (uint32_t)ld(&O->a), cb = (uint32_t)ld(&O->b);
       const ZZEdge* ed = A.edges + first;
-      int cnt[NR];
+      const uint32_t jt = (uint32_t)jk[0];
+      int sum_a = 0, dcls[7];
+      int e = 0;
 #pragma unroll
-      for (int k = 0; k < NR; ++k) cnt[k] = 0;
-      for (int e = 0; e < count; ++e) {
-        const int lu = ld(&ed[e].lu), lv = ld(&ed[e].lv), u = ld(&ed[e].u), vv = ld(&ed[e].v);
-#pragma unroll
-        for (int k = 0; k < NR; ++k) cnt[k] += gbit(jk[k], lu, u) ^ gbit(jk[k], lv, vv);
+      for (int c = 0; c < 7; ++c) {
+        const int nc = (int)(((c < 4 ? ca : cb) >> (8 * (c & 3))) & 255u);
+        int a_c = 0;
+        for (int i = 0; i < nc; ++i, ++e) {
+          const uint32_t tm = ld(&ed[e].tmask);
+          const uint64_t om = ld(&ed[e].omask);
+          a_c += (__popc(jt & tm) + __popcll(base & om)) & 1;
+        }
+        sum_a += a_c;
+        dcls[c] = nc - 2 * a_c;
       }
 #pragma unroll
       for (int k = 0; k < NR; ++k) {
-        const C p = ldc(T + mat + cnt[k]);
+        int cnt = sum_a;
+#pragma unroll
+        for (int c = 1; c < 7; ++c)
+          if (__builtin_popcount(k & c) & 1) cnt += dcls[c];
+        const C p = tab(mat + cnt);
         if (ADJ) {
-          if (gen >= 0) acc += (double)ldc(T + gen + cnt[k]).x * im_conj_mul(w[k], v[k]);
+          if (gen >= 0) acc += (double)tab(gen + cnt).x * im_conj_mul(w[k], v[k]);
           w[k] = cmul(w[k], p);
         }
         v[k] = cmul(v[k], p);
@@ -1072,7 +1098,8 @@ template <typename R, int MAXM, bool ADJ>
 static hipError_t rb_launch_one(const PassArgs& A, dim3 grid, hipStream_t s) {
   constexpr size_t bytes = (size_t)(2 * sizeof(R)) * ((size_t)1 << MAXM);
   if constexpr (bytes <= 131072) {
-    tile_pass_rb<R, 3, MAXM, ADJ><<<grid, 1 << (MAXM - 3), 0, s>>>(A);
+    const size_t dyn = (size_t)(A.win_n > 0 ? A.win_n : 0) * 2 * sizeof(R);
+    tile_pass_rb<R, 3, MAXM, ADJ><<<grid, 1 << (MAXM - 3), dyn, s>>>(A);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -1094,12 +1121,13 @@ static hipError_t rb_dispatch(int maxm, const PassArgs& A, uint64_t n_tiles, int
 
 template <typename R, bool ADJ>
 static hipError_t rb_multi_dispatch(int maxm, const PassArgs* items, const uint32_t* prefix, int n_items,
-                                    uint32_t n_wg, hipStream_t s) {
+                                    uint32_t n_wg, int max_win, hipStream_t s) {
+  const size_t dyn = (size_t)(max_win > 0 ? max_win : 0) * 2 * sizeof(R);
   switch (maxm) {
 #define QSV_MULTI(M)                                                                                   \
   case M:                                                                                              \
     if constexpr ((size_t)(2 * sizeof(R)) * ((size_t)1 << M) <= 131072) {                              \
-      tile_pass_rb_multi<R, 3, M, ADJ><<<n_wg, 1 << (M - 3), 0, s>>>(items, prefix, n_items);          \
+      tile_pass_rb_multi<R, 3, M, ADJ><<<n_wg, 1 << (M - 3), dyn, s>>>(items, prefix, n_items);        \
       return hipGetLastError();                                                                        \
     }                                                                                                  \
     return hipErrorInvalidValue;
@@ -1110,11 +1138,12 @@ static hipError_t rb_multi_dispatch(int maxm, const PassArgs* items, const uint3
 }
 
 hipError_t launch_tile_pass_rb_multi(int dtype, bool adj, int maxm, const PassArgs* items, const uint32_t* prefix,
-                                     int n_items, uint32_t n_wg, hipStream_t s) {
-  if (dtype == 0) return adj ? rb_multi_dispatch<float, true>(maxm, items, prefix, n_items, n_wg, s)
-                             : rb_multi_dispatch<float, false>(maxm, items, prefix, n_items, n_wg, s);
-  return adj ? rb_multi_dispatch<double, true>(maxm, items, prefix, n_items, n_wg, s)
-             : rb_multi_dispatch<double, false>(maxm, items, prefix, n_items, n_wg, s);
+                                     int n_items, uint32_t n_wg, int max_win, hipStream_t s) {
+  if (max_win > kMaxWindow) return hipErrorInvalidValue;
+  if (dtype == 0) return adj ? rb_multi_dispatch<float, true>(maxm, items, prefix, n_items, n_wg, max_win, s)
+                             : rb_multi_dispatch<float, false>(maxm, items, prefix, n_items, n_wg, max_win, s);
+  return adj ? rb_multi_dispatch<double, true>(maxm, items, prefix, n_items, n_wg, max_win, s)
+             : rb_multi_dispatch<double, false>(maxm, items, prefix, n_items, n_wg, max_win, s);
 }
 
 hipError_t launch_pauli_apply_multi(int dtype, const PauliJob* jobs, const uint32_t* prefix, int n_jobs, uint32_t n_wg,
@@ -1159,6 +1188,7 @@ hipError_t launch_inner_product(int dtype, const void* a, const void* b, int n, 
 
 hipError_t launch_tile_pass_rb(int dtype, bool adj, int maxm, const PassArgs& A, uint64_t n_tiles, int batch,
                                hipStream_t s) {
+  if (A.win_n > kMaxWindow) return hipErrorInvalidValue;
   if (dtype == 0) return adj ? rb_dispatch<float, true>(maxm, A, n_tiles, batch, s)
                              : rb_dispatch<float, false>(maxm, A, n_tiles, batch, s);
   return adj ? rb_dispatch<double, true>(maxm, A, n_tiles, batch, s)

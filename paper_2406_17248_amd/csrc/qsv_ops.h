@@ -16,7 +16,9 @@ enum OpType : int32_t {
   OP_DIAG = 2,    // run of diagonal gates: DiagEntry[first .. first+count)
   OP_ZZ = 3,      // exp(-i theta/2 * sum_e Z_u Z_v) over EdgeTable[first .. first+count):
                   // amplitude x is multiplied by ctab[mat + c(x)], c(x) = #edges with
-                  // x_u != x_v
+                  // x_u != x_v.  In register-blocked passes the edges are sorted by class
+                  // (ZZEdge::tmask etc.) and a, b pack the edge count of classes 0-3 and 4-7
+                  // as bytes
   OP_REMAP = 4,   // register-blocked passes: move amplitudes through LDS so that the
                   // local bits in mask `a` become the register bits; `b` packs their
                   // positions in ascending order (p0 | p1 << 8 | p2 << 16)
@@ -68,10 +70,20 @@ struct DiagEntry {
 };
 
 // One edge of an OP_ZZ run: global qubits (u, v) and their local bits in the pass's tile
-// (lu, lv; -1 when outside the tile).
+// (lu, lv; -1 when outside the tile).  For register-blocked passes, in the register layout
+// in force when the op runs: tmask = the endpoints that are thread-index bits (local bit
+// positions), omask = the endpoints outside the tile (global bits); the endpoints that are
+// register bits define the edge's class, the 3-bit mask with bit r set for each endpoint on
+// register bit r.  The edge differs in register slot k iff
+// popcount(j_thread & tmask) + popcount(base & omask) + popcount(k & class) is odd.
 struct ZZEdge {
-  int32_t u, v, lu, lv;
+  int32_t  u, v, lu, lv;
+  uint32_t tmask, pad;
+  uint64_t omask;
 };
+
+// Largest ctab window (complex entries) a register-blocked pass stages in LDS.
+constexpr int kMaxWindow = 256;
 
 struct PassArgs {
   void*        psi;           // state(s), batch item b at psi + b * bstride amplitudes
@@ -91,8 +103,10 @@ struct PassArgs {
   int32_t      m;             // tile qubits = popcount(tile_mask)
   int32_t      n_pslots;
   int32_t      lr0;           // register-blocked passes: local register mask at load time
-  int32_t      pad0;
+  int32_t      win_n;         // register-blocked passes: ctab entries [win_lo, win_lo + win_n)
+                              // copied to LDS for per-lane table lookups (0: read ctab)
   int64_t      n_tiles;       // tiles of this state (column length of partials)
+  int64_t      win_lo;
 };
 
 // One circuit's share of a multi-circuit Pauli-sum pass: lambda = H psi and the
