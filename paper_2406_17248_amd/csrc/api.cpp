@@ -222,6 +222,7 @@ hipError_t launch_pass(const qsv_state* s, const DevPass& dp, PassArgs A, int ba
   A.lr0 = dp.lr0;
   A.win_lo = dp.win_lo;
   A.win_n = dp.rb ? dp.win_n : 0;
+  A.pass_pslots = adj ? dp.pslot_count : 0;
   const uint64_t tiles = 1ull << (s->n - dp.m);
   A.n_tiles = (int64_t)tiles;
   if (dp.rb) return launch_tile_pass_rb(s->dtype, adj, dp.maxm, A, tiles, batch, s->stream);

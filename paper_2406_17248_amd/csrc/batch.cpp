@@ -43,6 +43,7 @@ struct Round {
   std::vector<uint32_t> prefix;  // n_items + 1
   int maxm = 9;
   int max_win = 0;                       // largest ctab window of the items (LDS entries)
+  int max_pslots = 0;                    // adjoint: largest per-pass gradient slot count
   size_t items_off = 0, prefix_off = 0;  // byte offsets in the static device table
 };
 
@@ -251,6 +252,7 @@ void build(qsv_batch* b) {
         A.lr0 = dp.lr0;
         A.win_lo = dp.win_lo;
         A.win_n = dp.win_n;
+        A.pass_pslots = adjoint ? dp.pslot_count : 0;
         A.n_tiles = 1ll << (b->circ[i].n - dp.m);
         A.n_pslots = adjoint ? p.n_pslots : 0;
         // pointer fields hold offsets for now: fixed up once the device base is known
@@ -265,6 +267,7 @@ void build(qsv_batch* b) {
         rd.prefix.push_back(rd.prefix.back() + (uint32_t)A.n_tiles);
         rd.maxm = std::max(rd.maxm, dp.maxm);
         rd.max_win = std::max(rd.max_win, dp.win_n);
+        rd.max_pslots = std::max(rd.max_pslots, A.pass_pslots);
       }
       rd.items_off = align_up(st.size(), 256);
       st.resize(rd.items_off + rd.items.size() * sizeof(PassArgs));
@@ -326,7 +329,7 @@ void build(qsv_batch* b) {
     if (e != hipSuccess) break;
     e = launch_tile_pass_rb_multi(dt, false, rd.maxm, reinterpret_cast<const PassArgs*>(sbase + rd.items_off),
                                   reinterpret_cast<const uint32_t*>(sbase + rd.prefix_off), (int)rd.items.size(),
-                                  rd.prefix.back(), rd.max_win, b->stream);
+                                  rd.prefix.back(), rd.max_win, rd.max_pslots, b->stream);
   }
   if (e == hipSuccess)
     e = launch_pauli_apply_multi(dt, reinterpret_cast<const PauliJob*>(sbase + p_jobs),
@@ -335,7 +338,7 @@ void build(qsv_batch* b) {
     if (e != hipSuccess) break;
     e = launch_tile_pass_rb_multi(dt, true, rd.maxm, reinterpret_cast<const PassArgs*>(sbase + rd.items_off),
                                   reinterpret_cast<const uint32_t*>(sbase + rd.prefix_off), (int)rd.items.size(),
-                                  rd.prefix.back(), rd.max_win, b->stream);
+                                  rd.prefix.back(), rd.max_win, rd.max_pslots, b->stream);
   }
   if (e == hipSuccess)
     e = launch_reduce_segments(part, reinterpret_cast<const int64_t*>(sbase + seg_offs),

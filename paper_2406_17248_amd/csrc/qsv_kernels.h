@@ -15,9 +15,10 @@ hipError_t launch_tile_pass_rb(int dtype, bool adj, int maxm, const PassArgs& A,
                                hipStream_t s);
 // Multi-circuit variants (batched uneven circuits).
 constexpr int kPauliChunk = 4096;  // amplitudes per workgroup of the multi-circuit Pauli pass
-// max_win: the largest win_n of the items (dynamic LDS of every workgroup).
+// max_win / max_pslots: the largest win_n / pass_pslots of the items (they size the
+// dynamic LDS of every workgroup).
 hipError_t launch_tile_pass_rb_multi(int dtype, bool adj, int maxm, const PassArgs* items, const uint32_t* prefix,
-                                     int n_items, uint32_t n_wg, int max_win, hipStream_t s);
+                                     int n_items, uint32_t n_wg, int max_win, int max_pslots, hipStream_t s);
 hipError_t launch_pauli_apply_multi(int dtype, const PauliJob* jobs, const uint32_t* prefix, int n_jobs, uint32_t n_wg,
                                     hipStream_t s);
 hipError_t launch_reduce_segments(const double* in, const int64_t* offs, const int32_t* lens, const int32_t* strides,

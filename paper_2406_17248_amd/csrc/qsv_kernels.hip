@@ -14,6 +14,8 @@
 //  reduce_columns fixed-order fp64 sums of per-block partials (bitwise repeatable).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "qsv_kernels.h"
 
 namespace qsv {
@@ -422,8 +424,19 @@ __device__ __forceinline__ void reg1_dispatch(int i, C* v, C* w, const int* jk, 
 
 __device__ __forceinline__ int insert_zero(int t, int p) { return ((t >> p) << (p + 1)) | (t & ((1 << p) - 1)); }
 
-// Dynamic LDS of the register-blocked passes (ctab window), sized per launch.
+// Dynamic LDS of the register-blocked passes, sized per launch: the ctab window, then
+// (adjoint) the deferred gradient sums.
 extern __shared__ __align__(16) unsigned char qsv_dyn_lds[];
+template <typename R> __host__ __device__ constexpr size_t win_bytes(int win_n) {
+  return ((size_t)(win_n > 0 ? win_n : 0) * 2 * sizeof(R) + 15) & ~(size_t)15;
+}
+// Enough for every workgroup of a launch whose items have at most win_n window entries and
+// pslots gradient slots: an item defers its sums only when pslots x waves fits the cap.
+template <typename R> static size_t rb_dyn_lds(int maxm, bool adj, int win_n, int pslots) {
+  const int nw = (1 << (maxm - 3)) >= 64 ? (1 << (maxm - 3)) / 64 : 1;
+  const int sums = adj ? std::min(pslots * nw, kMaxDeferredSums) : 0;
+  return win_bytes<R>(win_n) + (size_t)(sums > 0 ? sums : 0) * sizeof(double);
+}
 
 // Sign-only diagonal entries in a register-blocked pass: bit k of the result is the
 // parity of the entries satisfied by register slot k, from the per-entry thread mask and
@@ -505,6 +518,10 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
   // a copy of their ctab window in dynamic LDS.
   C* win = reinterpret_cast<C*>(qsv_dyn_lds);
   const int win_n = A.win_n;
+  // adjoint: per-(slot, wave) gradient sums after the window, reduced at the end of the pass
+  constexpr int NW = NT >= 64 ? NT / 64 : 1;
+  const bool defer = ADJ && A.pass_pslots * NW <= kMaxDeferredSums;
+  double* gsum = reinterpret_cast<double*>(qsv_dyn_lds + win_bytes<R>(win_n));
   const int64_t win_lo = A.win_lo;
   for (int i = tid; i < win_n; i += NT) win[i] = T[win_lo + i];
   __syncthreads();
@@ -696,15 +713,27 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
     }
     if (ADJ && ld(&O->flush)) {
       const double sv = wave_sum(acc);
-      if ((tid & 63) == 0) red[tid >> 6] = sv;
-      __syncthreads();
-      if (tid == 0) {
-        double s = 0.0;
-        for (int q = 0; q < (NT >= 64 ? NT / 64 : 1); ++q) s += red[q];
-        A.partials[((int64_t)b * A.n_pslots + ld(&O->pslot)) * A.n_tiles + (int64_t)tile] = s;
+      if (defer) {
+        if ((tid & 63) == 0) gsum[ld(&O->pslot) * NW + (tid >> 6)] = sv;
+      } else {
+        if ((tid & 63) == 0) red[tid >> 6] = sv;
+        __syncthreads();
+        if (tid == 0) {
+          double s = 0.0;
+          for (int q = 0; q < NW; ++q) s += red[q];
+          A.partials[((int64_t)b * A.n_pslots + ld(&O->pslot)) * A.n_tiles + (int64_t)tile] = s;
+        }
+        __syncthreads();
       }
       acc = 0.0;
-      __syncthreads();
+    }
+  }
+  if (defer) {
+    __syncthreads();
+    for (int q = tid; q < A.pass_pslots; q += NT) {
+      double s = 0.0;
+      for (int w2 = 0; w2 < NW; ++w2) s += gsum[q * NW + w2];
+      A.partials[((int64_t)b * A.n_pslots + q) * A.n_tiles + (int64_t)tile] = s;
     }
   }
 
@@ -1098,7 +1127,7 @@ template <typename R, int MAXM, bool ADJ>
 static hipError_t rb_launch_one(const PassArgs& A, dim3 grid, hipStream_t s) {
   constexpr size_t bytes = (size_t)(2 * sizeof(R)) * ((size_t)1 << MAXM);
   if constexpr (bytes <= 131072) {
-    const size_t dyn = (size_t)(A.win_n > 0 ? A.win_n : 0) * 2 * sizeof(R);
+    const size_t dyn = rb_dyn_lds<R>(MAXM, ADJ, A.win_n, A.pass_pslots);
     tile_pass_rb<R, 3, MAXM, ADJ><<<grid, 1 << (MAXM - 3), dyn, s>>>(A);
     return hipGetLastError();
   } else {
@@ -1121,8 +1150,8 @@ static hipError_t rb_dispatch(int maxm, const PassArgs& A, uint64_t n_tiles, int
 
 template <typename R, bool ADJ>
 static hipError_t rb_multi_dispatch(int maxm, const PassArgs* items, const uint32_t* prefix, int n_items,
-                                    uint32_t n_wg, int max_win, hipStream_t s) {
-  const size_t dyn = (size_t)(max_win > 0 ? max_win : 0) * 2 * sizeof(R);
+                                    uint32_t n_wg, int max_win, int max_pslots, hipStream_t s) {
+  const size_t dyn = rb_dyn_lds<R>(maxm, ADJ, max_win, max_pslots);
   switch (maxm) {
 #define QSV_MULTI(M)                                                                                   \
   case M:                                                                                              \
@@ -1138,12 +1167,13 @@ static hipError_t rb_multi_dispatch(int maxm, const PassArgs* items, const uint3
 }
 
 hipError_t launch_tile_pass_rb_multi(int dtype, bool adj, int maxm, const PassArgs* items, const uint32_t* prefix,
-                                     int n_items, uint32_t n_wg, int max_win, hipStream_t s) {
+                                     int n_items, uint32_t n_wg, int max_win, int max_pslots, hipStream_t s) {
   if (max_win > kMaxWindow) return hipErrorInvalidValue;
-  if (dtype == 0) return adj ? rb_multi_dispatch<float, true>(maxm, items, prefix, n_items, n_wg, max_win, s)
-                             : rb_multi_dispatch<float, false>(maxm, items, prefix, n_items, n_wg, max_win, s);
-  return adj ? rb_multi_dispatch<double, true>(maxm, items, prefix, n_items, n_wg, max_win, s)
-             : rb_multi_dispatch<double, false>(maxm, items, prefix, n_items, n_wg, max_win, s);
+  if (dtype == 0)
+    return adj ? rb_multi_dispatch<float, true>(maxm, items, prefix, n_items, n_wg, max_win, max_pslots, s)
+               : rb_multi_dispatch<float, false>(maxm, items, prefix, n_items, n_wg, max_win, max_pslots, s);
+  return adj ? rb_multi_dispatch<double, true>(maxm, items, prefix, n_items, n_wg, max_win, max_pslots, s)
+             : rb_multi_dispatch<double, false>(maxm, items, prefix, n_items, n_wg, max_win, max_pslots, s);
 }
 
 hipError_t launch_pauli_apply_multi(int dtype, const PauliJob* jobs, const uint32_t* prefix, int n_jobs, uint32_t n_wg,

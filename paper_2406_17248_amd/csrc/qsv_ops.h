@@ -107,7 +107,14 @@ struct PassArgs {
                               // copied to LDS for per-lane table lookups (0: read ctab)
   int64_t      n_tiles;       // tiles of this state (column length of partials)
   int64_t      win_lo;
+  int32_t      pass_pslots;   // adjoint: gradient slots (pslot values) used by this pass
+  int32_t      pad1;
 };
+
+// Adjoint register-blocked passes keep each gradient slot's per-wave sums in LDS until the
+// end of the pass when pass_pslots x waves fits in this many doubles (else each slot is
+// reduced across the workgroup when it is complete).
+constexpr int kMaxDeferredSums = 2048;
 
 // One circuit's share of a multi-circuit Pauli-sum pass: lambda = H psi and the
 // expectation partials of 2^n amplitudes, in chunks of one workgroup each.
