@@ -695,11 +695,29 @@ struct PassEmitter {
         pending_touched |= p.touched;
         continue;
       }
-      if (pending_touched & p.nondiag) flush();
+      TileOp pre{};
+      bool has_pre = false;
+      if (pending_touched & p.nondiag) {
+        flush();
+        // a sign-only diagonal run right before an uncontrolled register gate rides on it
+        // (one op instead of two); it is applied to every slot before the gate
+        if (reg_index && p.type == P_DENSE1 && (p.cmask & ~T) == 0 && !plan.ops.empty() &&
+            plan.ops.back().type == OP_DIAG && plan.ops.back().b == 0 && op_param.back() < 0) {
+          pre = plan.ops.back();
+          plan.ops.pop_back();
+          op_param.pop_back();
+          has_pre = true;
+        }
+      }
       TileOp op{};
       op.gen = -1;
       op.pslot = -1;
       op.flush = 0;
+      if (has_pre) {
+        op.b = 1;
+        op.first = pre.first;
+        op.count = pre.count;
+      }
       op.type = p.type == P_DENSE1 ? OP_DENSE1 : OP_DENSE2;
       if (p.type == P_DENSE1 && reg_index) {
         op.a = reg_index[loc[p.q0]];

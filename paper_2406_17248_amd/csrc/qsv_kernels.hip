@@ -551,6 +551,19 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
     const int type = ld(&O->type);
     const uint64_t omask = ld(&O->omask);
     const bool on = (base & omask) == omask;
+    // sign flips only (Z, CZ, multi-controlled Z), alone (DIAG with b = 0) or ahead of a
+    // gate (DENSE1 with b = 1): the parity of the satisfied entries, as one bit per
+    // register slot (slot 0 holds the thread's own local index)
+    const int ob = ld(&O->b);
+    if (on && active && ((type == OP_DIAG && !ob) || (type == OP_DENSE1 && ob))) {
+      const uint32_t sm = sign_slots(A.diag + ld(&O->first), ld(&O->count), base, (uint32_t)jk[0]);
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const uint32_t f = (sm << (31 - k)) & 0x80000000u;
+        flip_sign(v[k], f);
+        if (ADJ) flip_sign(w[k], f);
+      }
+    }
     if (type == OP_REMAP) {
       int jn[NR];
       layout(ld(&O->a), jn);
@@ -626,17 +639,7 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
       };
       apply_staged(v);
       if (ADJ) apply_staged(w);
-    } else if (on && active && type == OP_DIAG && !ld(&O->b)) {
-      // sign flips only (Z, CZ, multi-controlled Z): the parity of the satisfied entries,
-      // as one bit per register slot (slot 0 holds the thread's own local index)
-      const uint32_t sm = sign_slots(A.diag + ld(&O->first), ld(&O->count), base, (uint32_t)jk[0]);
-#pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        const uint32_t f = (sm << (31 - k)) & 0x80000000u;
-        flip_sign(v[k], f);
-        if (ADJ) flip_sign(w[k], f);
-      }
-    } else if (on && active && type == OP_DIAG) {
+    } else if (on && active && type == OP_DIAG && ob) {
       const int first = ld(&O->first), count = ld(&O->count);
       C ph[NR];
       double gw[NR];

@@ -23,9 +23,11 @@ enum OpType : int32_t {
                   // local bits in mask `a` become the register bits; `b` packs their
                   // positions in ascending order (p0 | p1 << 8 | p2 << 16)
 };
-// In register-blocked passes each thread holds 2^RB amplitudes; DENSE1/DENSE2 then name
-// register-bit indices (a, b in [0, RB)) instead of local bits, and the other ops are
-// elementwise.  The initial (load) layout is PassArgs::lr0.
+// In register-blocked passes each thread holds 2^RB amplitudes; DENSE1 then names a
+// register-bit index (a in [0, RB)) instead of a local bit, and the other ops are
+// elementwise.  A DENSE1 op with b = 1 first applies the sign-only diagonal run
+// DiagEntry[first .. first+count) (the flush that the gate required).  The initial (load)
+// layout is PassArgs::lr0.
 
 // Matrices, phases and generator weights live in a per-batch-item table of complex
 // numbers (ctab); ops refer to it by offset.
