@@ -728,6 +728,7 @@ struct PassEmitter {
       }
       op.lmask = local_mask(p.cmask & T);
       op.omask = p.cmask & ~T;
+      if (reg_index && op.omask) op.lmask |= kHasOutsideControls;
       op.mat = alloc(prim_size(p));
       plan.fills.push_back({F_PRIM_MATRIX, pi, 0, op.mat});
       int32_t prm = -1;

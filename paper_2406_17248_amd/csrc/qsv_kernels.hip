@@ -471,7 +471,8 @@ __device__ __forceinline__ uint32_t sign_slots(const DiagEntry* d, int count, ui
   return sm;
 }
 
-template <typename R, int RB, int MAXM, bool ADJ>
+// FULL: the tile fills the workgroup (m == MAXM), so every thread holds amplitudes.
+template <typename R, int RB, int MAXM, bool ADJ, bool FULL>
 __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, const int b) {
   using C = typename CT<R>::T;
   static_assert(RB == 3, "layouts are encoded with three register bits");
@@ -484,7 +485,7 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
   const int tid = threadIdx.x;
   const int m = A.m;
   const int nloc = 1 << m;
-  const bool active = tid < (nloc >> RB);
+  const bool active = FULL || tid < (nloc >> RB);
   const uint64_t TM = A.tile_mask;
   const uint64_t full = (A.n_qubits >= 64) ? ~0ull : ((1ull << A.n_qubits) - 1);
   const uint64_t base = pdep64(tile, full & ~TM);
@@ -546,11 +547,16 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
   auto gbit = [&](int j, int l, int q) -> int { return l >= 0 ? (j >> l) & 1 : (int)((base >> q) & 1); };
 
   double acc = 0.0;
-  for (int oi = 0; oi < A.n_ops; ++oi) {
-    const TileOp* O = A.ops + oi;
+  const TileOp* O = A.ops;
+  for (int oi = 0; oi < A.n_ops; ++oi, ++O) {
     const int type = ld(&O->type);
-    const uint64_t omask = ld(&O->omask);
-    const bool on = (base & omask) == omask;
+    const uint32_t lm_raw = ld(&O->lmask);
+    bool on = true;
+    if (lm_raw & kHasOutsideControls) {
+      const uint64_t omask = ld(&O->omask);
+      on = (base & omask) == omask;
+    }
+    const uint32_t lmask = lm_raw & ~kHasOutsideControls;
     // sign flips only (Z, CZ, multi-controlled Z), alone (DIAG with b = 0) or ahead of a
     // gate (DENSE1 with b = 1): the parity of the satisfied entries, as one bit per
     // register slot (slot 0 holds the thread's own local index)
@@ -601,13 +607,13 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
 #pragma unroll
         for (int r = 0; r < 4; ++r) G[r] = ldc(T + gen + r);
       }
-      reg1_dispatch<RB, ADJ>(ld(&O->a), v, w, jk, ld(&O->lmask), U, grad, G, acc);
+      reg1_dispatch<RB, ADJ>(ld(&O->a), v, w, jk, lmask, U, grad, G, acc);
     } else if (on && type == OP_DENSE2) {
       // two-qubit dense gate on local bits a, b, applied to the tile staged in LDS (no
       // gradient: parameterized two-qubit rotations are lowered to RZZ with basis changes)
       const int a = ld(&O->a), bb = ld(&O->b), mat = ld(&O->mat);
       const int lo = a < bb ? a : bb, hi = a < bb ? bb : a;
-      const uint32_t lm = ld(&O->lmask);
+      const uint32_t lm = lmask;
       auto apply_staged = [&](C (&reg)[NR]) {
         if (active) {
 #pragma unroll
@@ -753,7 +759,7 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
 
 template <typename R, int RB, int MAXM, bool ADJ>
 __global__ __launch_bounds__(1 << (MAXM - RB)) void tile_pass_rb(PassArgs A) {
-  rb_body<R, RB, MAXM, ADJ>(A, blockIdx.x, blockIdx.y);
+  rb_body<R, RB, MAXM, ADJ, true>(A, blockIdx.x, blockIdx.y);
 }
 
 // Many circuits in one launch: item i owns workgroups [prefix[i], prefix[i+1]); each
@@ -768,7 +774,7 @@ __global__ __launch_bounds__(1 << (MAXM - RB)) void tile_pass_rb_multi(const Pas
     if (ld(prefix + mid) <= w) lo = mid; else hi = mid;
   }
   const PassArgs A = items[lo];
-  rb_body<R, RB, MAXM, ADJ>(A, (uint64_t)(w - ld(prefix + lo)), 0);
+  rb_body<R, RB, MAXM, ADJ, false>(A, (uint64_t)(w - ld(prefix + lo)), 0);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1221,6 +1227,7 @@ hipError_t launch_inner_product(int dtype, const void* a, const void* b, int n, 
 
 hipError_t launch_tile_pass_rb(int dtype, bool adj, int maxm, const PassArgs& A, uint64_t n_tiles, int batch,
                                hipStream_t s) {
+  if (A.m != maxm) return hipErrorInvalidValue;  // the kernel assumes a full workgroup
   if (A.win_n > kMaxWindow) return hipErrorInvalidValue;
   if (dtype == 0) return adj ? rb_dispatch<float, true>(maxm, A, n_tiles, batch, s)
                              : rb_dispatch<float, false>(maxm, A, n_tiles, batch, s);

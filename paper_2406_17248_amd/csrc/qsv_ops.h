@@ -31,6 +31,10 @@ enum OpType : int32_t {
 
 // Matrices, phases and generator weights live in a per-batch-item table of complex
 // numbers (ctab); ops refer to it by offset.
+// Register-blocked passes: bit 31 of TileOp::lmask is set when omask is not 0, so ops
+// without outside controls skip reading it.
+constexpr uint32_t kHasOutsideControls = 0x80000000u;
+
 struct TileOp {
   int32_t  type;
   int32_t  a, b;       // local target bits (DENSE1 / DENSE2)
