@@ -133,6 +133,41 @@ def qaoa_leg(Q, dtype, ps_sets):
             "max_grad_diff_over_S": agree, "param_shift_sets": ps_sets}
 
 
+def batch_leg(Q, reps=5):
+    """512 uneven circuits (8-20 qubits, depth 2-10, 50 Pauli strings each), complex64:
+    energy and adjoint gradient of every circuit from one HIP-graph replay, after the
+    autotuner picks the tile width; compared with the same circuits one call at a time."""
+    import numpy as np
+
+    import workloads as W
+    circs, hams, params = W.uneven_batch_workload()
+    b = Q.qsv_batch_create(circs, hams, "c64")
+    tile = Q.qsv_batch_autotune(b, params)
+    Q.qsv_batch_expectation_and_grad(b, params)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        E, g = Q.qsv_batch_expectation_and_grad(b, params)
+    t_batch = (time.perf_counter() - t0) / reps
+    dev_ms = b.info()["last_ms"]
+    states = {}
+    for i, c in enumerate(circs):
+        n = c["n_qubits"]
+        if n not in states:
+            states[n] = Q.qsv_state_create(n, "c64")
+    t0 = time.perf_counter()
+    worst = 0.0
+    for i, c in enumerate(circs):
+        p_i = params[b.offsets[i]:b.offsets[i + 1]]
+        Ei, gi = Q.qsv_expectation_and_grad(states[c["n_qubits"]], c, hams[i], p_i)
+        worst = max(worst, abs(Ei - E[i]))
+    t_single = time.perf_counter() - t0
+    del states, b
+    return {"workload": "uneven512_hea_n8-20_depth2-10_50terms", "dtype": "c64", "autotuned_tile": tile,
+            "circuits_per_s": len(circs) / t_batch, "ms_per_batch": t_batch * 1e3, "graph_replay_device_ms": dev_ms,
+            "one_call_per_circuit_ms": t_single * 1e3, "speedup_vs_one_call_per_circuit": t_single / t_batch,
+            "max_energy_diff_vs_one_call": worst}
+
+
 def max_cut(edges, n_nodes):
     """Brute-force maximum cut of a small graph (all 2^n bipartitions)."""
     import numpy as np
@@ -290,6 +325,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-qaoa", action="store_true")
     ap.add_argument("--no-other-dtype", action="store_true", help="skip the second precision")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-circuit batch leg")
     ap.add_argument("--with-copy", action="store_true",
                     help="after the timed steps, run one plain state copy (counter calibration)")
     ap.add_argument("--ps-sets", type=int, default=1)
@@ -349,6 +385,11 @@ def main():
                 out["qaoa"].append(qaoa_leg(Q, dt_, args.ps_sets))
             except Exception as ex:  # report, do not hide, a failure of the secondary leg
                 out["qaoa"].append({"dtype": dt_, "error": repr(ex)})
+    if not args.no_batch:
+        try:
+            out["batch"] = batch_leg(Q)
+        except Exception as ex:  # report, do not hide, a failure of the secondary leg
+            out["batch"] = {"error": repr(ex)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, single thread)")
         out["cpu_baseline"] = run_cpu_baseline(n, depth, args.cpu_seconds)
