@@ -1,4 +1,5 @@
 // C ABI of the engine: state management, uploads, pass orchestration, reductions.
+#include <algorithm>
 #include <hip/hip_runtime_api.h>
 
 #include <cmath>
@@ -352,6 +353,7 @@ void run_pauli(qsv_state* s, const DevPauli& dp, const void* psi, void* lam, int
     A.accumulate = g > 0 ? 1 : 0;
     A.col = 2 * g;
     A.ncols = 2 * G;
+    A.real_coeffs = std::all_of(dp.groups[g].cim.begin(), dp.groups[g].cim.end(), [](double c) { return c == 0.0; });
     // read psi; write lambda (and read it when accumulating)
     const double sb = (double)batch * (double)s->namps() * (double)s->amp_bytes();
     const double bytes = sb * (1.0 + (lam ? 1.0 : 0.0) + (lam && g > 0 ? 1.0 : 0.0));

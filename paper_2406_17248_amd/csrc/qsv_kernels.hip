@@ -877,7 +877,47 @@ __global__ __launch_bounds__(256) void pauli_group(PauliGroupArgs A) {
   const uint64_t N = 1ull << A.n_qubits;
   const uint64_t stride = (uint64_t)gridDim.x * 256;
   double er = 0.0, ei = 0.0;
-  if (A.xmask == 0) {
+  if (A.xmask == 0 && A.n_qubits >= 2) {
+    // Diagonal group, four consecutive amplitudes per thread: a term's sign parity on the
+    // shared high bits is computed once; the two low bits flip it by the uniform pattern
+    // pat(z) (bit j set when popcount(j & z) is odd).
+    const bool real_c = A.real_coeffs;
+    for (uint64_t q = (uint64_t)blockIdx.x * 256 + threadIdx.x; q < (N >> 2); q += stride) {
+      const uint64_t x0 = q << 2;
+      C v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = psi[x0 + j];
+      double fr[4] = {0.0, 0.0, 0.0, 0.0}, fi[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int k = 0; k < A.n_terms; ++k) {
+        const uint64_t z = ld(A.zmasks + k);
+        const double cr = ld(A.cre + k);
+        const uint32_t zl = (uint32_t)z & 3u;
+        const uint32_t pat = (zl == 0u) ? 0u : (zl == 1u) ? 0xAu : (zl == 2u) ? 0xCu : 0x6u;
+        const uint32_t par = (uint32_t)(__popcll(x0 & z) & 1) ? 0xFu : 0u;
+        const uint32_t sg = par ^ pat;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fr[j] += ((sg >> j) & 1u) ? -cr : cr;
+        if (!real_c) {
+          const double ci = ld(A.cim + k);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) fi[j] += ((sg >> j) & 1u) ? -ci : ci;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double pj = (double)v[j].x * v[j].x + (double)v[j].y * v[j].y;
+        er += pj * fr[j];
+        ei += pj * fi[j];
+        if (lam) {
+          C o;
+          o.x = (R)(fr[j] * v[j].x - fi[j] * v[j].y);
+          o.y = (R)(fr[j] * v[j].y + fi[j] * v[j].x);
+          if (A.accumulate) { const C l = lam[x0 + j]; o.x += l.x; o.y += l.y; }
+          lam[x0 + j] = o;
+        }
+      }
+    }
+  } else if (A.xmask == 0) {
     for (uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x; x < N; x += stride) {
       double fr, fi;
       group_factor<R>(A, x, fr, fi);

@@ -151,7 +151,7 @@ struct PauliGroupArgs {
   int32_t      accumulate;    // lam += (1) or lam = (0)
   int32_t      col;           // first partial column (real part; imaginary part at col + 1)
   int32_t      ncols;
-  int32_t      pad;
+  int32_t      real_coeffs;   // 1 when every cim is 0 (the imaginary part is not accumulated)
 };
 
 }  // namespace qsv
