@@ -167,6 +167,7 @@ struct Uploaded {
   TileOp* ops = nullptr;
   DiagEntry* diag = nullptr;
   ZZEdge* edges = nullptr;
+  uint64_t* deps = nullptr;
   void* ctab = nullptr;
   int64_t ctab_stride = 0;  // complex entries per batch item
 };
@@ -181,12 +182,13 @@ struct UploadReq {
 void upload_plans(qsv_state* s, const UploadReq* reqs, int n_req, Uploaded* out) {
   const size_t cs = s->amp_bytes();
   size_t off = 0;
-  std::vector<size_t> o_ops(n_req), o_diag(n_req), o_edges(n_req), o_ctab(n_req);
+  std::vector<size_t> o_ops(n_req), o_diag(n_req), o_edges(n_req), o_deps(n_req), o_ctab(n_req);
   for (int r = 0; r < n_req; ++r) {
     const Plan& p = *reqs[r].plan;
     o_ops[r] = off; off = align_up(off + p.ops.size() * sizeof(TileOp), 256);
     o_diag[r] = off; off = align_up(off + p.diag.size() * sizeof(DiagEntry), 256);
     o_edges[r] = off; off = align_up(off + p.edges.size() * sizeof(ZZEdge), 256);
+    o_deps[r] = off; off = align_up(off + p.deps.size() * sizeof(uint64_t), 256);
     o_ctab[r] = off; off = align_up(off + (size_t)reqs[r].batch * p.ctab_size * cs, 256);
   }
   const size_t total = off ? off : 256;
@@ -196,6 +198,7 @@ void upload_plans(qsv_state* s, const UploadReq* reqs, int n_req, Uploaded* out)
     if (!p.ops.empty()) std::memcpy(st + o_ops[r], p.ops.data(), p.ops.size() * sizeof(TileOp));
     if (!p.diag.empty()) std::memcpy(st + o_diag[r], p.diag.data(), p.diag.size() * sizeof(DiagEntry));
     if (!p.edges.empty()) std::memcpy(st + o_edges[r], p.edges.data(), p.edges.size() * sizeof(ZZEdge));
+    if (!p.deps.empty()) std::memcpy(st + o_deps[r], p.deps.data(), p.deps.size() * sizeof(uint64_t));
     const std::vector<cplx>& ct = *reqs[r].ctab;
     const size_t ne = (size_t)reqs[r].batch * p.ctab_size;
     if (s->dtype == QSV_C64) {
@@ -214,6 +217,7 @@ void upload_plans(qsv_state* s, const UploadReq* reqs, int n_req, Uploaded* out)
     out[r].ops = reinterpret_cast<TileOp*>(d + o_ops[r]);
     out[r].diag = reinterpret_cast<DiagEntry*>(d + o_diag[r]);
     out[r].edges = reinterpret_cast<ZZEdge*>(d + o_edges[r]);
+    out[r].deps = reinterpret_cast<uint64_t*>(d + o_deps[r]);
     out[r].ctab = d + o_ctab[r];
     out[r].ctab_stride = reqs[r].plan->ctab_size;
   }
@@ -271,6 +275,7 @@ void run_forward(qsv_state* s, const Plan& p, const Uploaded& u, void* psi, int6
     A.ops = u.ops + dp.op_first;
     A.diag = u.diag;
     A.edges = u.edges;
+    A.dep = u.deps + dp.dep_first;
     A.ctab = u.ctab;
     A.ctab_bstride = u.ctab_stride;
     A.partials = nullptr;
@@ -389,6 +394,7 @@ void run_adjoint(qsv_state* s, const Plan& adj, const Uploaded& u, void* psi, vo
     A.ops = u.ops + ap.op_first;
     A.diag = u.diag;
     A.edges = u.edges;
+    A.dep = u.deps + ap.dep_first;
     A.ctab = u.ctab;
     A.ctab_bstride = u.ctab_stride;
     A.partials = static_cast<double*>(s->gpart.p) + (size_t)ap.pslot_first * tiles;

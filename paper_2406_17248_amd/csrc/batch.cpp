@@ -144,7 +144,7 @@ void build(qsv_batch* b) {
     if (bytes) std::memcpy(st.data() + off, p, bytes);
     return off;
   };
-  struct PlanOffs { size_t ops, diag, edges; };
+  struct PlanOffs { size_t ops, diag, edges, deps; };
   std::vector<PlanOffs> fo(nc), ao(nc);
   for (size_t i = 0; i < nc; ++i) {
     for (int k = 0; k < 2; ++k) {
@@ -153,6 +153,7 @@ void build(qsv_batch* b) {
       o.ops = put(p.ops.data(), p.ops.size() * sizeof(TileOp));
       o.diag = put(p.diag.data(), p.diag.size() * sizeof(DiagEntry));
       o.edges = put(p.edges.data(), p.edges.size() * sizeof(ZZEdge));
+      o.deps = put(p.deps.data(), p.deps.size() * sizeof(uint64_t));
     }
   }
   // Pauli terms and jobs
@@ -260,6 +261,8 @@ void build(qsv_batch* b) {
         A.ops = reinterpret_cast<const TileOp*>((uintptr_t)((adjoint ? ao[i] : fo[i]).ops + dp.op_first * sizeof(TileOp)));
         A.diag = reinterpret_cast<const DiagEntry*>((uintptr_t)(adjoint ? ao[i] : fo[i]).diag);
         A.edges = reinterpret_cast<const ZZEdge*>((uintptr_t)(adjoint ? ao[i] : fo[i]).edges);
+        A.dep = reinterpret_cast<const uint64_t*>(
+            (uintptr_t)((adjoint ? ao[i] : fo[i]).deps + (size_t)dp.dep_first * sizeof(uint64_t)));
         A.ctab = reinterpret_cast<const void*>((uintptr_t)(adjoint ? b->ctab_adj_off[i] : b->ctab_fwd_off[i]));
         A.partials = adjoint ? reinterpret_cast<double*>((uintptr_t)(g_off[i] + (int64_t)dp.pslot_first * atiles[i]))
                              : nullptr;
@@ -293,6 +296,7 @@ void build(qsv_batch* b) {
         A.ops = reinterpret_cast<const TileOp*>(sbase + (uintptr_t)A.ops);
         A.diag = reinterpret_cast<const DiagEntry*>(sbase + (uintptr_t)A.diag);
         A.edges = reinterpret_cast<const ZZEdge*>(sbase + (uintptr_t)A.edges);
+        A.dep = reinterpret_cast<const uint64_t*>(sbase + (uintptr_t)A.dep);
         A.ctab = cbase + (uintptr_t)A.ctab * b->amp();
         A.ctab_bstride = 0;
         if (pass == 1) A.partials = part + (uintptr_t)A.partials;

@@ -961,6 +961,17 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
     }
     dp.op_count = (int32_t)plan.ops.size() - dp.op_first;
     if (rb) {
+      dp.dep_first = (int32_t)plan.deps.size();
+      auto deposit = [&](uint64_t v) {
+        uint64_t r = 0, m = ps.tile_mask;
+        for (; m && v; v >>= 1, m &= m - 1)
+          if (v & 1) r |= m & (~m + 1);
+        return r;
+      };
+      for (int i = 0; i < 128; ++i) plan.deps.push_back(deposit((uint64_t)i));
+      for (int i = 0; i < 128; ++i) plan.deps.push_back(deposit((uint64_t)i << 7));
+    }
+    if (rb) {
       // ctab window of the per-lane lookups (ZZ phase / generator tables, phase entries)
       int64_t lo = INT64_MAX, hi = INT64_MIN;
       auto cover = [&](int64_t off, int64_t n) {

@@ -87,6 +87,7 @@ struct DevPass {
   int32_t  op_first, op_count;
   int32_t  pslot_first, pslot_count;
   int32_t  win_lo, win_n;  // register-blocked: ctab window of the pass's per-lane lookups
+  int32_t  dep_first;      // register-blocked: first of the pass's 256 Plan::deps entries
 };
 
 // A fully planned execution (forward or adjoint reverse sweep) of one circuit structure.
@@ -96,6 +97,9 @@ struct Plan {
   int32_t n_qubits = 0;
   std::vector<Prim> prims;
   std::vector<DevPass> passes;
+  // register-blocked passes: global-index deposits of local indices, 256 per pass
+  // (entry i < 128: local bits 0..6 = i; entry 128 + i: local bits 7..13 = i)
+  std::vector<uint64_t> deps;
   std::vector<TileOp> ops;
   std::vector<DiagEntry> diag;
   std::vector<ZZEdge> edges;

@@ -505,15 +505,11 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
     for (int k = 0; k < NR; ++k) jo[k] = jt | ((k & 1) << p0) | (((k >> 1) & 1) << p1) | (((k >> 2) & 1) << p2);
   };
   // Global index of a local index: two lookup tables of deposits into the tile mask
-  // (local bits 0..6 and 7..13), built once per workgroup.
+  // (local bits 0..6 and 7..13), computed by the planner for the pass.
   __shared__ uint64_t dep_lo[128], dep_hi[128];
-  if (tid < 128) {
-    dep_lo[tid] = pdep64((uint64_t)tid, TM);
-    dep_hi[tid] = pdep64((uint64_t)tid << 7, TM);
-  }
-  for (int i = tid + NT; i < 128; i += NT) {
-    dep_lo[i] = pdep64((uint64_t)i, TM);
-    dep_hi[i] = pdep64((uint64_t)i << 7, TM);
+  for (int i = tid; i < 128; i += NT) {
+    dep_lo[i] = A.dep[i];
+    dep_hi[i] = A.dep[128 + i];
   }
   // The pass's per-lane table lookups (ZZ phases and generator weights, phase entries) read
   // a copy of their ctab window in dynamic LDS.

@@ -100,6 +100,7 @@ struct PassArgs {
   const TileOp*    ops;
   const DiagEntry* diag;
   const ZZEdge*    edges;
+  const uint64_t*  dep;       // register-blocked: 256 deposits of local indices (see Plan::deps)
   const void*  ctab;          // per batch item: ctab + b * ctab_bstride complex entries
   int64_t      ctab_bstride;
   double*      partials;      // adjoint: [batch][n_pslots][n_tiles]
