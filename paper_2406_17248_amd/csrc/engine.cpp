@@ -970,6 +970,22 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
       };
       for (int i = 0; i < 128; ++i) plan.deps.push_back(deposit((uint64_t)i));
       for (int i = 0; i < 128; ++i) plan.deps.push_back(deposit((uint64_t)i << 7));
+      // contiguous runs of the bits outside the tile, lowest first
+      const uint64_t outside = (n >= 64 ? ~0ull : ((1ull << n) - 1)) & ~ps.tile_mask;
+      std::vector<uint64_t> runs;
+      int shift = 0;
+      for (int q = 0; q < n;) {
+        if (!(outside >> q & 1)) { ++q; continue; }
+        int len = 0;
+        while (q + len < n && (outside >> (q + len) & 1)) ++len;
+        runs.push_back((uint64_t)q | (uint64_t)len << 8 | (uint64_t)shift << 16);
+        shift += len;
+        q += len;
+      }
+      if ((int)runs.size() + 257 > kDepEntries) fail(QSV_EINVAL, "internal: too many runs of outside bits");
+      plan.deps.push_back(runs.size());
+      plan.deps.insert(plan.deps.end(), runs.begin(), runs.end());
+      plan.deps.resize(dp.dep_first + kDepEntries, 0);
     }
     if (rb) {
       // ctab window of the per-lane lookups (ZZ phase / generator tables, phase entries)

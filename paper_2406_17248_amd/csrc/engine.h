@@ -97,8 +97,10 @@ struct Plan {
   int32_t n_qubits = 0;
   std::vector<Prim> prims;
   std::vector<DevPass> passes;
-  // register-blocked passes: global-index deposits of local indices, 256 per pass
-  // (entry i < 128: local bits 0..6 = i; entry 128 + i: local bits 7..13 = i)
+  // register-blocked passes, kDepEntries per pass: global-index deposits of local indices
+  // (entry i < 128: local bits 0..6 = i; entry 128 + i: local bits 7..13 = i), then the
+  // number of contiguous runs of bits outside the tile and one entry per run,
+  // lo | len << 8 | shift << 16: tile t has base = OR_r ((t >> shift) & (2^len - 1)) << lo
   std::vector<uint64_t> deps;
   std::vector<TileOp> ops;
   std::vector<DiagEntry> diag;

@@ -487,8 +487,16 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
   const int nloc = 1 << m;
   const bool active = FULL || tid < (nloc >> RB);
   const uint64_t TM = A.tile_mask;
-  const uint64_t full = (A.n_qubits >= 64) ? ~0ull : ((1ull << A.n_qubits) - 1);
-  const uint64_t base = pdep64(tile, full & ~TM);
+  // the tile's bits outside the tile mask, from the planner's contiguous runs
+  uint64_t base = 0;
+  {
+    const int nruns = (int)ld(A.dep + 256);
+    for (int r = 0; r < nruns; ++r) {
+      const uint64_t e = ld(A.dep + 257 + r);
+      const int lo = (int)(e & 255), len = (int)((e >> 8) & 255), sh = (int)((e >> 16) & 255);
+      base |= ((tile >> sh) & ((1ull << len) - 1)) << lo;
+    }
+  }
 
   C* psi = reinterpret_cast<C*>(A.psi) + (int64_t)b * A.bstride;
   C* lam = ADJ ? reinterpret_cast<C*>(A.lam) + (int64_t)b * A.bstride : nullptr;

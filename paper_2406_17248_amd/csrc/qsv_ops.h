@@ -88,6 +88,9 @@ struct ZZEdge {
   uint64_t omask;
 };
 
+// Planner tables per register-blocked pass: 256 deposits, a run count, up to 63 runs.
+constexpr int kDepEntries = 320;
+
 // Largest ctab window (complex entries) a register-blocked pass stages in LDS.
 constexpr int kMaxWindow = 256;
 
@@ -100,7 +103,8 @@ struct PassArgs {
   const TileOp*    ops;
   const DiagEntry* diag;
   const ZZEdge*    edges;
-  const uint64_t*  dep;       // register-blocked: 256 deposits of local indices (see Plan::deps)
+  const uint64_t*  dep;       // register-blocked: kDepEntries per pass (deposits of local
+                              // indices, 256 entries; runs of outside bits, from entry 256)
   const void*  ctab;          // per batch item: ctab + b * ctab_bstride complex entries
   int64_t      ctab_bstride;
   double*      partials;      // adjoint: [batch][n_pslots][n_tiles]
