@@ -144,7 +144,10 @@ PlanOptions plan_options(const qsv_state* s, bool adjoint, bool fuse_zz) {
   // variant stages psi and lambda together
   if (std::min<int>(o.tile_qubits, s->n) < o.rb_min || rb_capacity_host(s->dtype, std::min<int>(o.tile_qubits, s->n)) < 0)
     o.tile_qubits = std::min<int>(o.tile_qubits, adjoint ? (s->dtype == QSV_C64 ? 12 : 11) : 13);
-  o.low_qubits = s->dtype == QSV_C64 ? 4 : 3;
+  // qubits every tile keeps for dense global accesses: measured on the 30-qubit brick and
+  // the 24-qubit QAOA batch (with XCD-ordered tiles, neighbouring tiles share cache lines
+  // in one XCD's L2, so keeping only qubit 0 costs less than the passes it saves)
+  o.low_qubits = adjoint && s->dtype == QSV_C128 ? 3 : 1;
   o.fuse_zz = fuse_zz;
   o.dtype = s->dtype;
   return o;

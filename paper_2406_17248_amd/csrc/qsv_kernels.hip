@@ -763,7 +763,12 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
 
 template <typename R, int RB, int MAXM, bool ADJ>
 __global__ __launch_bounds__(1 << (MAXM - RB)) void tile_pass_rb(PassArgs A) {
-  rb_body<R, RB, MAXM, ADJ, true>(A, blockIdx.x, blockIdx.y);
+  // Workgroups go to the 8 XCDs in turn; give each XCD a contiguous range of tiles, so
+  // tiles that share cache lines (they differ only in low qubits outside the tile) run
+  // back to back behind the same L2.
+  const uint32_t g = gridDim.x, w = blockIdx.x;
+  const uint64_t t = (g % 8 == 0) ? (uint64_t)(w & 7) * (g >> 3) + (w >> 3) : w;
+  rb_body<R, RB, MAXM, ADJ, true>(A, t, blockIdx.y);
 }
 
 // Many circuits in one launch: item i owns workgroups [prefix[i], prefix[i+1]); each
