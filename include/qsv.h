@@ -151,7 +151,7 @@ int qsv_state_copy(qsv_state* dst, const qsv_state* src);
 /* Execution options (integers).  Defaults are chosen per dtype and n. */
 enum qsv_option {
   QSV_OPT_TILE_QUBITS = 0,   /* qubits per fused LDS tile pass (0: per-gate kernels only);
-                                default 11; clamped to n */
+                                default 12 (c64) / 11 (c128); clamped to n */
   QSV_OPT_ADJ_TILE_QUBITS = 1, /* tile width of the adjoint reverse sweep (psi and lambda
                                   share LDS); default 10 (c64) / 11 (c128);
                                   complex128 is capped at 12 */

@@ -128,8 +128,8 @@ void stage_release_after_queue(qsv_state* s) {
 // Default options per dtype.
 void default_options(qsv_state* s) {
   // measured on the 30-qubit brick circuit (forward) and the 24-qubit QAOA batch (adjoint):
-  // narrower tiles cost a few more passes but far fewer diagonal flushes and remaps
-  s->opt[QSV_OPT_TILE_QUBITS] = 11;
+  // tiles wider than these save passes but need more REMAPs per pass
+  s->opt[QSV_OPT_TILE_QUBITS] = s->dtype == QSV_C64 ? 12 : 11;
   s->opt[QSV_OPT_ADJ_TILE_QUBITS] = s->dtype == QSV_C64 ? 10 : 11;
   s->opt[QSV_OPT_THREADS] = 512;
 }
@@ -150,6 +150,9 @@ PlanOptions plan_options(const qsv_state* s, bool adjoint, bool fuse_zz) {
   o.low_qubits = adjoint && s->dtype == QSV_C128 ? 3 : 1;
   o.fuse_zz = fuse_zz;
   o.dtype = s->dtype;
+  // complex64 forward passes keep 16 amplitudes per thread (registers still allow 4 waves
+  // per SIMD): fewer REMAPs and half the per-op and per-tile work per amplitude
+  if (!adjoint && s->dtype == QSV_C64) o.reg_bits = 4;
   return o;
 }
 
@@ -233,7 +236,7 @@ hipError_t launch_pass(const qsv_state* s, const DevPass& dp, PassArgs A, int ba
   A.pass_pslots = adj ? dp.pslot_count : 0;
   const uint64_t tiles = 1ull << (s->n - dp.m);
   A.n_tiles = (int64_t)tiles;
-  if (dp.rb) return launch_tile_pass_rb(s->dtype, adj, dp.maxm, A, tiles, batch, s->stream);
+  if (dp.rb) return launch_tile_pass_rb(s->dtype, adj, dp.rb, dp.maxm, A, tiles, batch, s->stream);
   return launch_tile_pass(s->dtype, adj, dp.maxm, A, tiles, batch, s->stream);
 }
 

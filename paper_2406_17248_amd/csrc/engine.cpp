@@ -529,8 +529,8 @@ static bool zz_fusable(const Prim& p, const qsv_circuit* c) {
   return p.recipe == M_GATE && p.cmask == 0 && c->gates[p.gate].kind == QSV_GATE_RZZ;
 }
 
-int rb_capacity_host(int dtype, int m) {
-  if (m < kRegBits + 1 || m > 13) return -1;
+int rb_capacity_host(int dtype, int m, int reg_bits) {
+  if (m < reg_bits + 1 || m > 13) return -1;
   const size_t amp = dtype == 0 ? 8 : 16;
   return amp * ((size_t)1 << m) <= 131072 ? m : -1;
 }
@@ -641,9 +641,9 @@ struct PassEmitter {
     for (int bit = 0; bit < 32; ++bit)
       if (lr >> bit & 1) pos[np++] = bit;
     d.kmask = 0;
-    for (int k = 0; k < (1 << kRegBits); ++k) {
+    for (int k = 0; k < (1 << np); ++k) {
       uint32_t bits = 0;
-      for (int i = 0; i < np && i < kRegBits; ++i) bits |= (uint32_t)((k >> i) & 1) << pos[i];
+      for (int i = 0; i < np; ++i) bits |= (uint32_t)((k >> i) & 1) << pos[i];
       if ((bits & rm) == rm) d.kmask |= 1u << k;
     }
   }
@@ -772,12 +772,21 @@ struct PassEmitter {
             // register-blocked: edges grouped by class, class sizes packed in a and b
             std::stable_sort(run.begin(), run.end(),
                              [](const ZZEdge& x, const ZZEdge& y) { return x.pad < y.pad; });
-            uint32_t n_cls[8] = {0};
-            for (const ZZEdge& ed : run) n_cls[ed.pad]++;
-            for (int c = 0; c < 8; ++c)
-              if (n_cls[c] > 255) fail(QSV_EINVAL, "internal: too many edges in one ZZ class");
-            op.a = (int32_t)(n_cls[0] | n_cls[1] << 8 | n_cls[2] << 16 | n_cls[3] << 24);
-            op.b = (int32_t)(n_cls[4] | n_cls[5] << 8 | n_cls[6] << 16 | n_cls[7] << 24);
+            // class masks with at most two bits in increasing order; the count of the
+            // i-th is byte i of (a, b, lmask)
+            std::vector<uint32_t> classes;
+            for (uint32_t c = 0; c < (1u << __builtin_popcount((uint32_t)cur_lr)); ++c)
+              if (__builtin_popcount(c) <= 2) classes.push_back(c);
+            uint32_t words[3] = {0, 0, 0};
+            for (size_t i = 0; i < classes.size(); ++i) {
+              uint32_t n_c = 0;
+              for (const ZZEdge& ed : run) n_c += ed.pad == classes[i];
+              if (n_c > 255 || (i == 11 && n_c > 127)) fail(QSV_EINVAL, "internal: too many edges in one ZZ class");
+              words[i >> 2] |= n_c << (8 * (i & 3));
+            }
+            op.a = (int32_t)words[0];
+            op.b = (int32_t)words[1];
+            op.lmask = words[2];
           }
           for (ZZEdge& ed : run) ed.pad = 0;
           plan.edges.insert(plan.edges.end(), run.begin(), run.end());
@@ -891,8 +900,10 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
   }
 
   const int m = std::min<int>(std::max(opt.tile_qubits, 2), n);
-  const bool rb = opt.use_rb && m >= opt.rb_min && rb_capacity_host(opt.dtype, m) >= 0;
-  const int maxm = rb ? std::max(m, kRegBits + 6) : tile_capacity_host(opt.dtype, adjoint, m);
+  // four register bits only for forward passes whose workgroup still fills a wave
+  const int reg_bits = (adjoint || std::min<int>(std::max(opt.tile_qubits, 2), n) < opt.reg_bits + 6) ? kRegBits : opt.reg_bits;
+  const bool rb = opt.use_rb && m >= opt.rb_min && rb_capacity_host(opt.dtype, m, reg_bits) >= 0;
+  const int maxm = rb ? std::max(m, reg_bits + 6) : tile_capacity_host(opt.dtype, adjoint, m);
   if (maxm < 0) fail(QSV_EINVAL, "tile width does not fit in LDS for this dtype");
   const std::vector<Pass> passes = plan_passes(plan.prims, n, m, opt.low_qubits);
   const int low_local = std::max(0, std::min(opt.low_qubits, m - 2));
@@ -902,7 +913,7 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
     dp.tile_mask = ps.tile_mask;
     dp.m = ps.m;
     dp.maxm = maxm;
-    dp.rb = rb ? 1 : 0;
+    dp.rb = rb ? reg_bits : 0;
     dp.op_first = (int32_t)plan.ops.size();
     dp.pslot_first = plan.n_pslots;
     PassEmitter em{plan, c, adjoint, opt, ps.tile_mask, {}, {}};
@@ -914,7 +925,7 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
       em.emit(ps.prims, nullptr);
       em.flush();
     } else {
-      const int r = kRegBits;
+      const int r = reg_bits;
       const std::vector<Pass> rounds = plan_rounds(plan.prims, ps.prims, ps.tile_mask, r);
       const int32_t top = ((1 << r) - 1) << (ps.m - r);  // load/store layout
       int32_t cur = -1;
@@ -1023,8 +1034,8 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
 std::string structure_key(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
   std::string key;
   auto put = [&](const void* p, size_t n) { key.append(reinterpret_cast<const char*>(p), n); };
-  const int32_t head[8] = {c->n_qubits, adjoint ? 1 : 0, opt.tile_qubits, opt.low_qubits, opt.fuse_zz ? 1 : 0,
-                           opt.dtype, opt.use_rb ? 1 : 0, opt.rb_min};
+  const int32_t head[9] = {c->n_qubits, adjoint ? 1 : 0, opt.tile_qubits, opt.low_qubits, opt.fuse_zz ? 1 : 0,
+                           opt.dtype, opt.use_rb ? 1 : 0, opt.rb_min, opt.reg_bits};
   put(head, sizeof(head));
   for (size_t i = 0; i < c->n_gates; ++i) {
     const qsv_gate& g = c->gates[i];

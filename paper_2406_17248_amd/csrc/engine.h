@@ -82,7 +82,7 @@ struct DevPass {
   uint64_t tile_mask;
   int32_t  m;
   int32_t  maxm;       // LDS capacity instantiation
-  int32_t  rb;         // 1: register-blocked kernel (3 register bits)
+  int32_t  rb;         // register-blocked kernel: its register bits (3 or 4); 0: LDS sweep
   int32_t  lr0;        // register-blocked: local register mask at load time
   int32_t  op_first, op_count;
   int32_t  pslot_first, pslot_count;
@@ -121,6 +121,7 @@ struct PlanOptions {
   int32_t dtype = 1;
   bool    use_rb = true;      // register-blocked kernel for tiles of rb_min..13 qubits
   int32_t rb_min = 9;         // smallest register-blocked tile (smaller ones idle threads)
+  int32_t reg_bits = 3;       // register bits of register-blocked passes (3, or 4 forward)
 };
 
 // Validate a circuit against n_params (and the state's n).  Throws Error.
@@ -140,9 +141,10 @@ std::vector<Pass> plan_passes(const std::vector<Prim>& prims, int32_t n, int32_t
 // (one for forward passes, psi and lambda for the adjoint) within 128 KiB, or -1.
 int tile_capacity_host(int dtype, bool adj, int m);
 
-// Register-blocked passes: 3 register bits; used for tiles of 9..13 qubits within 128 KiB.
+// Register-blocked passes: 3 register bits (4 for complex64 forward passes when asked
+// for); used for tiles of 9..13 qubits within 128 KiB.
 constexpr int kRegBits = 3;
-int rb_capacity_host(int dtype, int m);
+int rb_capacity_host(int dtype, int m, int reg_bits = kRegBits);
 
 // Register rounds of one register-blocked pass: groups of the pass's primitives whose
 // one-qubit dense targets fit in r register qubits (drawn from `allowed`).

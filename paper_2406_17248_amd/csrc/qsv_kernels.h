@@ -9,10 +9,11 @@ namespace qsv {
 
 hipError_t launch_tile_pass(int dtype, bool adj, int maxm, const PassArgs& A, uint64_t n_tiles,
                             int batch, hipStream_t s);
-// Register-blocked tile pass (3 register bits, 2^(maxm-3) threads, 2^maxm-amplitude LDS
-// exchange buffer, plus A.win_n ctab entries of dynamic LDS); maxm in [9, 13].
-hipError_t launch_tile_pass_rb(int dtype, bool adj, int maxm, const PassArgs& A, uint64_t n_tiles, int batch,
-                               hipStream_t s);
+// Register-blocked tile pass (reg_bits = 3, or 4 for complex64 forward passes; 2^(maxm -
+// reg_bits) threads, a 2^maxm-amplitude LDS exchange buffer, plus dynamic LDS for the ctab
+// window and deferred gradient sums); maxm in [9, 13] and equal to A.m.
+hipError_t launch_tile_pass_rb(int dtype, bool adj, int reg_bits, int maxm, const PassArgs& A, uint64_t n_tiles,
+                               int batch, hipStream_t s);
 // Multi-circuit variants (batched uneven circuits).
 constexpr int kPauliChunk = 4096;  // amplitudes per workgroup of the multi-circuit Pauli pass
 // max_win / max_pslots: the largest win_n / pass_pslots of the items (they size the

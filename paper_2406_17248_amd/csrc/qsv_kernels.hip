@@ -438,6 +438,13 @@ template <typename R> static size_t rb_dyn_lds(int maxm, bool adj, int win_n, in
   return win_bytes<R>(win_n) + (size_t)(sums > 0 ? sums : 0) * sizeof(double);
 }
 
+// ZZ edge classes of a register block of RB bits: the register-bit masks with at most two
+// bits set, in increasing order (the planner packs class sizes in this order).
+template <int RB> __host__ __device__ constexpr int zz_classes() { return RB == 3 ? 7 : 11; }
+template <int RB> __host__ __device__ constexpr int zz_class(int i) {
+  return RB == 3 ? i : (i < 7 ? i : (i == 7 ? 8 : (i == 8 ? 9 : (i == 9 ? 10 : 12))));
+}
+
 // Sign-only diagonal entries in a register-blocked pass: bit k of the result is the
 // parity of the entries satisfied by register slot k, from the per-entry thread mask and
 // slot set (jt = the thread's local index with its register bits zero).
@@ -475,7 +482,7 @@ __device__ __forceinline__ uint32_t sign_slots(const DiagEntry* d, int count, ui
 template <typename R, int RB, int MAXM, bool ADJ, bool FULL>
 __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, const int b) {
   using C = typename CT<R>::T;
-  static_assert(RB == 3, "layouts are encoded with three register bits");
+  static_assert(RB == 3 || RB == 4, "register blocks of three or four bits");
   constexpr int NT = 1 << (MAXM - RB);
   constexpr int NR = 1 << RB;
   constexpr int S = sizeof(R) == 8 ? 3 : 4;
@@ -503,14 +510,27 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
   const C* src = A.src ? reinterpret_cast<const C*>(A.src) + (int64_t)b * A.src_bstride : psi;
   const C* T = reinterpret_cast<const C*>(A.ctab) + (int64_t)b * A.ctab_bstride;
 
-  // Local index of register slot k: the thread id with zeros inserted at the three
-  // register bits, plus k spread over them.
+  // Local index of register slot k: the thread id with zeros inserted at the RB register
+  // bits (ascending), plus the bits of k spread over them.
   int jk[NR];
   auto layout = [&](int lr, int* jo) {
-    const int p0 = __builtin_ctz(lr), p1 = __builtin_ctz(lr & (lr - 1)), p2 = 31 - __builtin_clz(lr);
-    const int jt = insert_zero(insert_zero(insert_zero(tid, p0), p1), p2);
+    int pos[RB];
+    int rest = lr;
 #pragma unroll
-    for (int k = 0; k < NR; ++k) jo[k] = jt | ((k & 1) << p0) | (((k >> 1) & 1) << p1) | (((k >> 2) & 1) << p2);
+    for (int i = 0; i < RB; ++i) {
+      pos[i] = __builtin_ctz(rest);
+      rest &= rest - 1;
+    }
+    int jt = tid;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) jt = insert_zero(jt, pos[i]);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      int j = jt;
+#pragma unroll
+      for (int i = 0; i < RB; ++i) j |= ((k >> i) & 1) << pos[i];
+      jo[k] = j;
+    }
   };
   // Global index of a local index: two lookup tables of deposits into the tile mask
   // (local bits 0..6 and 7..13), computed by the planner for the pass.
@@ -692,15 +712,18 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
       // class c; an edge of class c differs in slot k iff its thread/outside parity
       // differs from the parity of (k & c), so with a_c = the class's edges whose
       // thread/outside parity is odd, c(slot k) = sum_c a_c + sum_{c: k & c odd} (n_c - 2 a_c).
+      // classes are register-bit masks of at most two bits, listed by zz_class<RB>(i); the
+      // edge count of class i is byte i of (a, b, lmask)
       const int first = ld(&O->first), mat = ld(&O->mat), gen = ld(&O->gen);
-      const uint32_t ca = (uint32_t)ld(&O->a), cb = (uint32_t)ld(&O->b);
+      const uint32_t cw[3] = {(uint32_t)ld(&O->a), (uint32_t)ld(&O->b), lm_raw};
       const ZZEdge* ed = A.edges + first;
       const uint32_t jt = (uint32_t)jk[0];
-      int sum_a = 0, dcls[7];
+      constexpr int NCLS = zz_classes<RB>();
+      int sum_a = 0, dcls[NCLS];
       int e = 0;
 #pragma unroll
-      for (int c = 0; c < 7; ++c) {
-        const int nc = (int)(((c < 4 ? ca : cb) >> (8 * (c & 3))) & 255u);
+      for (int c = 0; c < NCLS; ++c) {
+        const int nc = (int)((cw[c >> 2] >> (8 * (c & 3))) & 255u);
         int a_c = 0;
         for (int i = 0; i < nc; ++i, ++e) {
           const uint32_t tm = ld(&ed[e].tmask);
@@ -714,8 +737,8 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
       for (int k = 0; k < NR; ++k) {
         int cnt = sum_a;
 #pragma unroll
-        for (int c = 1; c < 7; ++c)
-          if (__builtin_popcount(k & c) & 1) cnt += dcls[c];
+        for (int c = 1; c < NCLS; ++c)
+          if (__builtin_popcount(k & zz_class<RB>(c)) & 1) cnt += dcls[c];
         const C p = tab(mat + cnt);
         if (ADJ) {
           if (gen >= 0) acc += (double)tab(gen + cnt).x * im_conj_mul(w[k], v[k]);
@@ -1181,29 +1204,38 @@ static hipError_t tile_dispatch(int maxm, const PassArgs& A, uint64_t n_tiles, i
   }
 }
 
-template <typename R, int MAXM, bool ADJ>
+template <typename R, int RB, int MAXM, bool ADJ>
 static hipError_t rb_launch_one(const PassArgs& A, dim3 grid, hipStream_t s) {
   constexpr size_t bytes = (size_t)(2 * sizeof(R)) * ((size_t)1 << MAXM);
-  if constexpr (bytes <= 131072) {
+  // four register bits: complex64 forward passes only (their registers allow 4 waves/SIMD)
+  if constexpr (bytes <= 131072 && (RB == 3 || (!ADJ && sizeof(R) == 4 && MAXM >= 10))) {
     const size_t dyn = rb_dyn_lds<R>(MAXM, ADJ, A.win_n, A.pass_pslots);
-    tile_pass_rb<R, 3, MAXM, ADJ><<<grid, 1 << (MAXM - 3), dyn, s>>>(A);
+    tile_pass_rb<R, RB, MAXM, ADJ><<<grid, 1 << (MAXM - RB), dyn, s>>>(A);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
   }
 }
 
-template <typename R, bool ADJ>
-static hipError_t rb_dispatch(int maxm, const PassArgs& A, uint64_t n_tiles, int batch, hipStream_t s) {
-  const dim3 grid((unsigned)n_tiles, (unsigned)batch);
+template <typename R, bool ADJ, int RB>
+static hipError_t rb_dispatch_rb(int maxm, const PassArgs& A, dim3 grid, hipStream_t s) {
   switch (maxm) {
-    case 9:  return rb_launch_one<R, 9, ADJ>(A, grid, s);
-    case 10: return rb_launch_one<R, 10, ADJ>(A, grid, s);
-    case 11: return rb_launch_one<R, 11, ADJ>(A, grid, s);
-    case 12: return rb_launch_one<R, 12, ADJ>(A, grid, s);
-    case 13: return rb_launch_one<R, 13, ADJ>(A, grid, s);
+    case 9:  return rb_launch_one<R, RB, 9, ADJ>(A, grid, s);
+    case 10: return rb_launch_one<R, RB, 10, ADJ>(A, grid, s);
+    case 11: return rb_launch_one<R, RB, 11, ADJ>(A, grid, s);
+    case 12: return rb_launch_one<R, RB, 12, ADJ>(A, grid, s);
+    case 13: return rb_launch_one<R, RB, 13, ADJ>(A, grid, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <typename R, bool ADJ>
+static hipError_t rb_dispatch(int reg_bits, int maxm, const PassArgs& A, uint64_t n_tiles, int batch,
+                              hipStream_t s) {
+  const dim3 grid((unsigned)n_tiles, (unsigned)batch);
+  if (reg_bits == 3) return rb_dispatch_rb<R, ADJ, 3>(maxm, A, grid, s);
+  if (reg_bits == 4) return rb_dispatch_rb<R, ADJ, 4>(maxm, A, grid, s);
+  return hipErrorInvalidValue;
 }
 
 template <typename R, bool ADJ>
@@ -1274,14 +1306,14 @@ hipError_t launch_inner_product(int dtype, const void* a, const void* b, int n, 
   return hipGetLastError();
 }
 
-hipError_t launch_tile_pass_rb(int dtype, bool adj, int maxm, const PassArgs& A, uint64_t n_tiles, int batch,
-                               hipStream_t s) {
+hipError_t launch_tile_pass_rb(int dtype, bool adj, int reg_bits, int maxm, const PassArgs& A, uint64_t n_tiles,
+                               int batch, hipStream_t s) {
   if (A.m != maxm) return hipErrorInvalidValue;  // the kernel assumes a full workgroup
   if (A.win_n > kMaxWindow) return hipErrorInvalidValue;
-  if (dtype == 0) return adj ? rb_dispatch<float, true>(maxm, A, n_tiles, batch, s)
-                             : rb_dispatch<float, false>(maxm, A, n_tiles, batch, s);
-  return adj ? rb_dispatch<double, true>(maxm, A, n_tiles, batch, s)
-             : rb_dispatch<double, false>(maxm, A, n_tiles, batch, s);
+  if (dtype == 0) return adj ? rb_dispatch<float, true>(reg_bits, maxm, A, n_tiles, batch, s)
+                             : rb_dispatch<float, false>(reg_bits, maxm, A, n_tiles, batch, s);
+  return adj ? rb_dispatch<double, true>(reg_bits, maxm, A, n_tiles, batch, s)
+             : rb_dispatch<double, false>(reg_bits, maxm, A, n_tiles, batch, s);
 }
 
 hipError_t launch_tile_pass(int dtype, bool adj, int maxm, const PassArgs& A, uint64_t n_tiles,
