@@ -17,11 +17,11 @@ enum OpType : int32_t {
   OP_ZZ = 3,      // exp(-i theta/2 * sum_e Z_u Z_v) over EdgeTable[first .. first+count):
                   // amplitude x is multiplied by ctab[mat + c(x)], c(x) = #edges with
                   // x_u != x_v.  In register-blocked passes the edges are sorted by class
-                  // (ZZEdge::tmask etc.) and a, b pack the edge count of classes 0-3 and 4-7
-                  // as bytes
+                  // (ZZEdge::tmask etc.): class i (the i-th register-bit mask with at most
+                  // two bits) has byte i of (a, b, lmask) edges
   OP_REMAP = 4,   // register-blocked passes: move amplitudes through LDS so that the
                   // local bits in mask `a` become the register bits; `b` packs their
-                  // positions in ascending order (p0 | p1 << 8 | p2 << 16)
+                  // positions in ascending order, 8 bits each
 };
 // In register-blocked passes each thread holds 2^RB amplitudes; DENSE1 then names a
 // register-bit index (a in [0, RB)) instead of a local bit, and the other ops are
