@@ -146,8 +146,9 @@ PlanOptions plan_options(const qsv_state* s, bool adjoint, bool fuse_zz) {
     o.tile_qubits = std::min<int>(o.tile_qubits, adjoint ? (s->dtype == QSV_C64 ? 12 : 11) : 13);
   // qubits every tile keeps for dense global accesses: measured on the 30-qubit brick and
   // the 24-qubit QAOA batch (with XCD-ordered tiles, neighbouring tiles share cache lines
-  // in one XCD's L2, so keeping only qubit 0 costs less than the passes it saves)
-  o.low_qubits = adjoint && s->dtype == QSV_C128 ? 3 : 1;
+  // in one XCD's L2, so keeping only the lowest qubits costs less than the passes it saves;
+  // complex64 forward passes keep two, below which partial-line writes grow by 40 %)
+  o.low_qubits = adjoint ? (s->dtype == QSV_C128 ? 3 : 1) : (s->dtype == QSV_C64 ? 2 : 1);
   o.fuse_zz = fuse_zz;
   o.dtype = s->dtype;
   // complex64 forward passes keep 16 amplitudes per thread (registers still allow 4 waves
