@@ -12,6 +12,10 @@ SOURCES = ["qsv_kernels.hip", "engine.cpp", "api.cpp", "batch.cpp", "mpnn.hip"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # Keep branches on wave-uniform values (the op type of a fused pass) as plain scalar
+    # branches: structurizing them makes old and new register blocks live at once, and the
+    # pass then copies its whole register block after every op.
+    "-mllvm", "-structurizecfg-skip-uniform-regions=true",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -45,6 +45,68 @@ template <typename C> __device__ __forceinline__ double im_conj_mul(C w, C g) {
   return (double)w.x * (double)g.y - (double)w.y * (double)g.x;
 }
 
+// Register-resident updates.  A pass keeps each amplitude in the same registers from op to
+// op only if every op overwrites an input component with the one multiply-add that reads it
+// last.  So each output component is finished by a multiply-add on the component it
+// replaces; all other reads of the inputs feed partial sums that pass through an empty asm
+// first, which orders them before every finishing multiply-add.  That multiply-add is
+// itself an asm: the compiler's two-address form would tie the result to the partial sum's
+// register instead.
+template <typename R> __device__ __forceinline__ void order(R& a, R& b) { asm("" : "+v"(a), "+v"(b)); }
+template <typename R> __device__ __forceinline__ void order(R& a, R& b, double& e) {
+  asm("" : "+v"(a), "+v"(b), "+v"(e));
+}
+template <typename R> __device__ __forceinline__ void order(R& a, R& b, R& c, R& d) {
+  asm("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
+}
+template <typename R> __device__ __forceinline__ void order(R& a, R& b, R& c, R& d, double& e) {
+  asm("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d), "+v"(e));
+}
+// a * b + c; fma_s takes a wave-uniform a (an SGPR operand)
+__device__ __forceinline__ double fma_s(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "s"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ float fma_s(float a, float b, float c) {
+  float r;
+  asm("v_fma_f32 %0, %1, %2, %3" : "=v"(r) : "s"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ double fma_v(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ float fma_v(float a, float b, float c) {
+  float r;
+  asm("v_fma_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+// (a0, a1) <- (u00 a0 + u01 a1, u10 a0 + u11 a1) in place, u wave-uniform.  The optional
+// `pin` (a value computed from the old inputs, e.g. a gradient term) is held back with
+// the partial sums, so it too is computed before any input is overwritten.
+template <typename C, typename... Pin>
+__device__ __forceinline__ void apply2(C u00, C u01, C u10, C u11, C& a0, C& a1, Pin&... pin) {
+  auto p0r = fmaT(-u00.y, a0.y, fmaT(u01.x, a1.x, -u01.y * a1.y));
+  auto p0i = fmaT(u00.y, a0.x, fmaT(u01.x, a1.y, u01.y * a1.x));
+  auto p1r = fmaT(u10.x, a0.x, fmaT(-u10.y, a0.y, -u11.y * a1.y));
+  auto p1i = fmaT(u10.x, a0.y, fmaT(u10.y, a0.x, u11.y * a1.x));
+  order(p0r, p0i, p1r, p1i, pin...);
+  a0.x = fma_s(u00.x, a0.x, p0r);
+  a0.y = fma_s(u00.x, a0.y, p0i);
+  a1.x = fma_s(u11.x, a1.x, p1r);
+  a1.y = fma_s(u11.x, a1.y, p1i);
+}
+// a <- a * p in place (p per lane), with an optional `pin` as above
+template <typename C, typename... Pin> __device__ __forceinline__ void cmul_in(C& a, C p, Pin&... pin) {
+  auto pr = -a.y * p.y;
+  auto pi = a.x * p.y;
+  order(pr, pi, pin...);
+  a.x = fma_v(p.x, a.x, pr);
+  a.y = fma_v(p.x, a.y, pi);
+}
+
 // Negate v when f is 0x80000000 (f = 0: unchanged), by flipping the sign bits.
 __device__ __forceinline__ void flip_sign(float2& v, uint32_t f) {
   v.x = __uint_as_float(__float_as_uint(v.x) ^ f);
@@ -366,15 +428,15 @@ __device__ __forceinline__ void reg1(C* v, C* w, const int* jk, uint32_t lm, con
     for (int k = 0; k < NR; ++k) {
       if (k & (1 << I)) continue;
       const int k1 = k | (1 << I);
-      const C a0 = v[k], a1 = v[k1];
       if (ADJ) {
-        const C b0 = w[k], b1 = w[k1];
-        if (grad) acc += im_conj_mul(b0, cdot2(G[0], a0, G[1], a1)) + im_conj_mul(b1, cdot2(G[2], a0, G[3], a1));
-        w[k] = cdot2(U[0], b0, U[1], b1);
-        w[k1] = cdot2(U[2], b0, U[3], b1);
+        double g = 0.0;
+        if (grad) g = im_conj_mul(w[k], cdot2(G[0], v[k], G[1], v[k1])) + im_conj_mul(w[k1], cdot2(G[2], v[k], G[3], v[k1]));
+        apply2(U[0], U[1], U[2], U[3], w[k], w[k1], g);
+        apply2(U[0], U[1], U[2], U[3], v[k], v[k1], g);
+        acc += g;
+      } else {
+        apply2(U[0], U[1], U[2], U[3], v[k], v[k1]);
       }
-      v[k] = cdot2(U[0], a0, U[1], a1);
-      v[k1] = cdot2(U[2], a0, U[3], a1);
     }
     return;
   }
@@ -383,18 +445,19 @@ __device__ __forceinline__ void reg1(C* v, C* w, const int* jk, uint32_t lm, con
     if (k & (1 << I)) continue;
     const int k1 = k | (1 << I);
     const bool ok = ((uint32_t)jk[k] & lm) == lm;
-    const C a0 = v[k], a1 = v[k1];
+    C n0 = v[k], n1 = v[k1];
     if (ADJ) {
-      const C b0 = w[k], b1 = w[k1];
-      if (grad) {
-        const double g = im_conj_mul(b0, cdot2(G[0], a0, G[1], a1)) + im_conj_mul(b1, cdot2(G[2], a0, G[3], a1));
-        acc += ok ? g : 0.0;
-      }
-      w[k] = csel(ok, cdot2(U[0], b0, U[1], b1), b0);
-      w[k1] = csel(ok, cdot2(U[2], b0, U[3], b1), b1);
+      C m0 = w[k], m1 = w[k1];
+      double g = 0.0;
+      if (grad) g = im_conj_mul(m0, cdot2(G[0], n0, G[1], n1)) + im_conj_mul(m1, cdot2(G[2], n0, G[3], n1));
+      apply2(U[0], U[1], U[2], U[3], m0, m1, g);
+      acc += ok ? g : 0.0;
+      w[k] = csel(ok, m0, w[k]);
+      w[k1] = csel(ok, m1, w[k1]);
     }
-    v[k] = csel(ok, cdot2(U[0], a0, U[1], a1), a0);
-    v[k1] = csel(ok, cdot2(U[2], a0, U[3], a1), a1);
+    apply2(U[0], U[1], U[2], U[3], n0, n1);
+    v[k] = csel(ok, n0, v[k]);
+    v[k1] = csel(ok, n1, v[k1]);
   }
 }
 
@@ -702,10 +765,13 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
         C p = ph[k];
         flip_sign(p, (sm << (31 - k)) & 0x80000000u);
         if (ADJ) {
-          acc += gw[k] * im_conj_mul(w[k], v[k]);
-          w[k] = cmul(w[k], p);
+          double g = gw[k] * im_conj_mul(w[k], v[k]);
+          cmul_in(w[k], p, g);
+          cmul_in(v[k], p, g);
+          acc += g;
+        } else {
+          cmul_in(v[k], p);
         }
-        v[k] = cmul(v[k], p);
       }
     } else if (on && active && type == OP_ZZ) {
       // c(x) = number of edges whose endpoints differ.  Edges come grouped by register
@@ -741,10 +807,14 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
           if (__builtin_popcount(k & zz_class<RB>(c)) & 1) cnt += dcls[c];
         const C p = tab(mat + cnt);
         if (ADJ) {
-          if (gen >= 0) acc += (double)tab(gen + cnt).x * im_conj_mul(w[k], v[k]);
-          w[k] = cmul(w[k], p);
+          double g = 0.0;
+          if (gen >= 0) g = (double)tab(gen + cnt).x * im_conj_mul(w[k], v[k]);
+          cmul_in(w[k], p, g);
+          cmul_in(v[k], p, g);
+          acc += g;
+        } else {
+          cmul_in(v[k], p);
         }
-        v[k] = cmul(v[k], p);
       }
     }
     if (ADJ && ld(&O->flush)) {
