@@ -523,21 +523,30 @@ static_assert(offsetof(DiagEntry, tmask) == offsetof(DiagEntry, ocmask) + 8 &&
 __device__ __forceinline__ SignFields sign_fields(const DiagEntry* d) {
   return ld_record(reinterpret_cast<const SignFields*>(&d->ocmask));
 }
-__device__ __forceinline__ uint32_t sign_slots(const DiagEntry* d, int count, uint64_t base, uint32_t jt) {
-  uint32_t sm = 0;
+// Also returns in `touched` (wave-uniform) the slots any entry of the run can flip.
+__device__ __forceinline__ uint32_t sign_slots(const DiagEntry* d, int count, uint64_t base, uint32_t jt,
+                                               uint32_t& touched) {
+  uint32_t sm = 0, any = 0;
   int e = 0;
   for (; e + 4 <= count; e += 4) {
     SignFields f[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) f[i] = sign_fields(d + e + i);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if ((base & f[i].ocmask) == f[i].ocmask && (jt & f[i].tmask) == f[i].tmask) sm ^= f[i].kmask;
+    for (int i = 0; i < 4; ++i) {
+      // entries with an outside control that is 0 in this tile do nothing
+      const uint32_t km = f[i].kmask & (0u - (uint32_t)((base & f[i].ocmask) == f[i].ocmask));
+      any |= km;
+      sm ^= (jt & f[i].tmask) == f[i].tmask ? km : 0u;
+    }
   }
   for (; e < count; ++e) {
     const SignFields f = sign_fields(d + e);
-    if ((base & f.ocmask) == f.ocmask && (jt & f.tmask) == f.tmask) sm ^= f.kmask;
+    const uint32_t km = f.kmask & (0u - (uint32_t)((base & f.ocmask) == f.ocmask));
+    any |= km;
+    sm ^= (jt & f.tmask) == f.tmask ? km : 0u;
   }
+  touched = any;
   return sm;
 }
 
@@ -595,6 +604,28 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
       jo[k] = j;
     }
   };
+  // LDS byte address of register slot k.  swz is linear over GF(2) and slot k's local index is
+  // the thread part (slot 0) with the bits of k spread over the register bits, so the address
+  // is a per-thread term, swz(thread part), XOR a wave-uniform term, swz(spread of k): moving
+  // a register block through LDS costs one XOR per slot.
+  auto slot_offsets = [&](int lr, int* off) {
+    int u[RB];
+    int rest = lr;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      u[i] = swz<S>(1 << __builtin_ctz(rest)) * (int)sizeof(C);
+      rest &= rest - 1;
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      int o = 0;
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+        if ((k >> i) & 1) o ^= u[i];
+      off[k] = o;
+    }
+  };
+  auto lds_at = [&](int byte_off) -> C& { return *reinterpret_cast<C*>(reinterpret_cast<char*>(buf) + byte_off); };
   // Global index of a local index: two lookup tables of deposits into the tile mask
   // (local bits 0..6 and 7..13), computed by the planner for the pass.
   __shared__ uint64_t dep_lo[128], dep_hi[128];
@@ -619,6 +650,8 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
     for (int k = 0; k < NR; ++k) xo[k] = base | dep_lo[jk[k] & 127] | dep_hi[jk[k] >> 7];
   };
   layout(A.lr0, jk);
+  int lr_cur = A.lr0;                                  // register bits of the current layout
+  int sw_cur = swz<S>(jk[0]) * (int)sizeof(C);         // per-thread term of its LDS addresses
 
   C v[NR], w[NR];
   if (active) {
@@ -649,40 +682,50 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
     // register slot (slot 0 holds the thread's own local index)
     const int ob = ld(&O->b);
     if (on && active && ((type == OP_DIAG && !ob) || (type == OP_DENSE1 && ob))) {
-      const uint32_t sm = sign_slots(A.diag + ld(&O->first), ld(&O->count), base, (uint32_t)jk[0]);
+      uint32_t touched;
+      const uint32_t sm = sign_slots(A.diag + ld(&O->first), ld(&O->count), base, (uint32_t)jk[0], touched);
+      // slots no entry can reach are skipped (a wave-uniform test): an entry on a register
+      // bit reaches half of them
 #pragma unroll
       for (int k = 0; k < NR; ++k) {
+        if (!((touched >> k) & 1u)) continue;
         const uint32_t f = (sm << (31 - k)) & 0x80000000u;
         flip_sign(v[k], f);
         if (ADJ) flip_sign(w[k], f);
       }
     }
     if (type == OP_REMAP) {
-      int jn[NR];
-      layout(ld(&O->a), jn);
+      const int lr = ld(&O->a);
+      int jn[NR], uo[NR], un[NR];
+      layout(lr, jn);
+      slot_offsets(lr_cur, uo);
+      slot_offsets(lr, un);
+      const int sw_new = swz<S>(jn[0]) * (int)sizeof(C);
       if (active) {
 #pragma unroll
-        for (int k = 0; k < NR; ++k) buf[swz<S>(jk[k])] = v[k];
+        for (int k = 0; k < NR; ++k) lds_at(sw_cur ^ uo[k]) = v[k];
       }
       __syncthreads();
       if (active) {
 #pragma unroll
-        for (int k = 0; k < NR; ++k) v[k] = buf[swz<S>(jn[k])];
+        for (int k = 0; k < NR; ++k) v[k] = lds_at(sw_new ^ un[k]);
       }
       if (ADJ) {
         __syncthreads();
         if (active) {
 #pragma unroll
-          for (int k = 0; k < NR; ++k) buf[swz<S>(jk[k])] = w[k];
+          for (int k = 0; k < NR; ++k) lds_at(sw_cur ^ uo[k]) = w[k];
         }
         __syncthreads();
         if (active) {
 #pragma unroll
-          for (int k = 0; k < NR; ++k) w[k] = buf[swz<S>(jn[k])];
+          for (int k = 0; k < NR; ++k) w[k] = lds_at(sw_new ^ un[k]);
         }
       }
 #pragma unroll
       for (int k = 0; k < NR; ++k) jk[k] = jn[k];
+      lr_cur = lr;
+      sw_cur = sw_new;
       __syncthreads();
     } else if (on && active && type == OP_DENSE1) {
       const int mat = ld(&O->mat), gen = ld(&O->gen);
@@ -701,10 +744,12 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
       const int a = ld(&O->a), bb = ld(&O->b), mat = ld(&O->mat);
       const int lo = a < bb ? a : bb, hi = a < bb ? bb : a;
       const uint32_t lm = lmask;
+      int uo[NR];
+      slot_offsets(lr_cur, uo);
       auto apply_staged = [&](C (&reg)[NR]) {
         if (active) {
 #pragma unroll
-          for (int k = 0; k < NR; ++k) buf[swz<S>(jk[k])] = reg[k];
+          for (int k = 0; k < NR; ++k) lds_at(sw_cur ^ uo[k]) = reg[k];
         }
         __syncthreads();
         for (int p = tid; p < (nloc >> 2); p += NT) {
@@ -726,7 +771,7 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
         __syncthreads();
         if (active) {
 #pragma unroll
-          for (int k = 0; k < NR; ++k) reg[k] = buf[swz<S>(jk[k])];
+          for (int k = 0; k < NR; ++k) reg[k] = lds_at(sw_cur ^ uo[k]);
         }
         __syncthreads();
       };
