@@ -158,7 +158,15 @@ enum qsv_option {
   QSV_OPT_THREADS = 2,       /* reserved (threads per tile workgroup follow the tile width) */
   QSV_OPT_PROFILE = 3,       /* 1: time every kernel launch with HIP events on the state's
                                 stream (read with qsv_profile_read); 0: off (default) */
-  QSV_OPT_COUNT = 4
+  QSV_OPT_RELAYOUT = 4,      /* 1 (default): qsv_apply_circuit runs fused passes out of place
+                                between the state and a scratch buffer of the same size
+                                (allocated on first use, freed with the state), storing each
+                                pass in a bit layout whose low bits are the next pass's tile so
+                                that every pass after the first reads contiguous blocks; the
+                                state is back in the natural layout when the call returns.
+                                Falls back to in-place passes if the scratch buffer cannot be
+                                allocated.  0: always in place */
+  QSV_OPT_COUNT = 5
 };
 int qsv_state_set_option(qsv_state* s, int32_t option, int64_t value);
 int qsv_state_get_option(const qsv_state* s, int32_t option, int64_t* value);

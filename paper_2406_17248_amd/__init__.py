@@ -9,7 +9,7 @@ been built (``paper_2406_17248_amd.build.build()``).
 from ._lib import (  # noqa: F401
     Batch, GATE_KIND, Mpnn, qsv_batch_autotune, qsv_batch_create, qsv_batch_expectation_and_grad,
     qsv_batch_set_tile, K_GATE_STREAM, K_OTHER, K_PAULI, K_TILE_ADJOINT, K_TILE_FORWARD, OPT_ADJ_TILE_QUBITS,
-    OPT_PROFILE, OPT_THREADS, OPT_TILE_QUBITS, QSV_C64, QSV_C128, Circuit,
+    OPT_PROFILE, OPT_RELAYOUT, OPT_THREADS, OPT_TILE_QUBITS, QSV_C64, QSV_C128, Circuit,
     PauliSum, QsvError, State, lib, qsv_apply_circuit, qsv_apply_pauli_sum, qsv_expectation,
     qsv_backward_batch, qsv_expectation_and_grad, qsv_expectation_and_grad_batch, qsv_expectation_batch,
     qsv_forward_batch, qsv_expectation_general, qsv_expectation_and_grad_multi,

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libqsv.so")
 
 QSV_OK, QSV_EINVAL, QSV_ENOMEM, QSV_EDTYPE, QSV_EHIP, QSV_ERANGE, QSV_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 QSV_C64, QSV_C128 = 0, 1
-OPT_TILE_QUBITS, OPT_ADJ_TILE_QUBITS, OPT_THREADS, OPT_PROFILE = 0, 1, 2, 3
+OPT_TILE_QUBITS, OPT_ADJ_TILE_QUBITS, OPT_THREADS, OPT_PROFILE, OPT_RELAYOUT = 0, 1, 2, 3, 4
 K_TILE_FORWARD, K_TILE_ADJOINT, K_PAULI, K_GATE_STREAM, K_OTHER = 0, 1, 2, 3, 4
 
 GATE_KIND = {

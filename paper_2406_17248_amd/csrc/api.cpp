@@ -37,7 +37,7 @@ struct qsv_state {
   void* psi = nullptr;
   bool owned = false;
   hipStream_t stream = nullptr;
-  int64_t opt[QSV_OPT_COUNT] = {0, 0, 0, 0};
+  int64_t opt[QSV_OPT_COUNT] = {0, 0, 0, 0, 0};
   // profiling: per kernel class, pending (start, stop) event pairs and bytes
   struct Rec { hipEvent_t a, b; int cls; double bytes; };
   std::vector<Rec> recs;
@@ -46,6 +46,8 @@ struct qsv_state {
   int64_t prof_n[QSV_K_COUNT] = {0, 0, 0, 0, 0};
   double prof_bytes[QSV_K_COUNT] = {0, 0, 0, 0, 0};
   DevBuf ws_psi, ws_lam, ws_aux1, ws_aux2, upload, partials, gpart, outbuf, pauli;
+  DevBuf relay;               // second state buffer of relayouting forward passes
+  bool relay_failed = false;  // its allocation failed once: run in place from then on
   // pinned staging for uploads and downloads, guarded by an event
   void* stage = nullptr;
   size_t stage_bytes = 0;
@@ -132,10 +134,12 @@ void default_options(qsv_state* s) {
   s->opt[QSV_OPT_TILE_QUBITS] = s->dtype == QSV_C64 ? 12 : 11;
   s->opt[QSV_OPT_ADJ_TILE_QUBITS] = s->dtype == QSV_C64 ? 10 : 11;
   s->opt[QSV_OPT_THREADS] = 512;
+  s->opt[QSV_OPT_RELAYOUT] = 1;
 }
 
-PlanOptions plan_options(const qsv_state* s, bool adjoint, bool fuse_zz) {
+PlanOptions plan_options(const qsv_state* s, bool adjoint, bool fuse_zz, bool relayout = false) {
   PlanOptions o;
+  o.relayout = relayout && !adjoint;
   o.tile_qubits = (int32_t)(adjoint ? s->opt[QSV_OPT_ADJ_TILE_QUBITS] : s->opt[QSV_OPT_TILE_QUBITS]);
   if (adjoint && o.tile_qubits == 0) o.tile_qubits = s->dtype == QSV_C64 ? 10 : 11;
   // complex128 adjoint tiles above 12 qubits would spill registers at 1024 threads
@@ -157,8 +161,8 @@ PlanOptions plan_options(const qsv_state* s, bool adjoint, bool fuse_zz) {
   return o;
 }
 
-const Plan& get_plan(qsv_state* s, const qsv_circuit* c, bool adjoint, bool fuse_zz) {
-  const PlanOptions o = plan_options(s, adjoint, fuse_zz);
+const Plan& get_plan(qsv_state* s, const qsv_circuit* c, bool adjoint, bool fuse_zz, bool relayout = false) {
+  const PlanOptions o = plan_options(s, adjoint, fuse_zz, relayout);
   std::string key = structure_key(c, adjoint, o);
   auto it = s->plans.find(key);
   if (it != s->plans.end()) return *it->second;
@@ -232,6 +236,7 @@ void upload_plans(qsv_state* s, const UploadReq* reqs, int n_req, Uploaded* out)
 
 hipError_t launch_pass(const qsv_state* s, const DevPass& dp, PassArgs A, int batch, bool adj) {
   A.lr0 = dp.lr0;
+  A.relayout = dp.rb ? dp.relayout : 0;
   A.win_lo = dp.win_lo;
   A.win_n = dp.rb ? dp.win_n : 0;
   A.pass_pslots = adj ? dp.pslot_count : 0;
@@ -271,10 +276,25 @@ void run_forward(qsv_state* s, const Plan& p, const Uploaded& u, void* psi, int6
     }
     return;
   }
+  // Relayouting plans alternate between psi and the scratch buffer so that the last pass
+  // writes psi (with an odd pass count the planner keeps the first pass in place).
+  const int np = (int)p.passes.size();
+  if (p.relayout && (batch != 1 || s->relay.bytes < s->namps() * s->amp_bytes()))
+    fail(QSV_EINVAL, "internal: relayout plan without its scratch buffer");
   bool first = true;
-  for (const DevPass& dp : p.passes) {
+  for (int pi = 0; pi < np; ++pi) {
+    const DevPass& dp = p.passes[pi];
+    void* in = psi;
+    void* out = nullptr;
+    if (p.relayout) {
+      void* other = s->relay.p;
+      in = (pi == 0 || (np - pi) % 2 == 0) ? psi : other;
+      out = ((np - 1 - pi) % 2 == 0) ? psi : other;
+      if (out == in) out = nullptr;
+    }
     PassArgs A{};
-    A.psi = psi;
+    A.psi = in;
+    A.dst = out;
     A.lam = nullptr;
     A.src = (first && src != psi) ? src : nullptr;
     A.bstride = bstride;
@@ -535,6 +555,7 @@ int qsv_state_destroy(qsv_state* s) {
     s->gpart.release();
     s->outbuf.release();
     s->pauli.release();
+    s->relay.release();
     if (s->stage) (void)hipHostFree(s->stage);
     if (s->stage_ev) (void)hipEventDestroy(s->stage_ev);
     for (auto& r : s->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
@@ -627,6 +648,8 @@ int qsv_state_set_option(qsv_state* s, int32_t option, int64_t value) {
       if (value != 256 && value != 512 && value != 1024) fail(QSV_EINVAL, "threads must be 256, 512 or 1024");
     } else if (option == QSV_OPT_PROFILE) {
       if (value != 0 && value != 1) fail(QSV_EINVAL, "profile must be 0 or 1");
+    } else if (option == QSV_OPT_RELAYOUT) {
+      if (value != 0 && value != 1) fail(QSV_EINVAL, "relayout must be 0 or 1");
     }
     s->opt[option] = value;
   });
@@ -645,7 +668,26 @@ int qsv_apply_circuit(qsv_state* s, const qsv_circuit* c, const double* params, 
     check_state(s);
     validate_circuit(c, params ? n_params : 0, s->n);
     set_device(s);
-    const Plan& p = get_plan(s, c, false, true);
+    bool relay = s->opt[QSV_OPT_RELAYOUT] != 0 && !s->relay_failed;
+    if (relay) {
+      // relayout only pays when the plan has several register-blocked passes
+      const Plan& probe = get_plan(s, c, false, true, true);
+      relay = probe.relayout;
+      const size_t need = s->namps() * s->amp_bytes();
+      if (relay && s->relay.bytes < need) {
+        s->relay.release();
+        void* ptr = nullptr;
+        if (hipMalloc(&ptr, need) == hipSuccess) {
+          s->relay.p = ptr;
+          s->relay.bytes = need;
+        } else {
+          (void)hipGetLastError();
+          s->relay_failed = true;
+          relay = false;
+        }
+      }
+    }
+    const Plan& p = get_plan(s, c, false, true, relay);
     std::vector<cplx> ctab(p.ctab_size);
     bind_ctab(p, c, params, nullptr, 0, ctab.data());
     Uploaded u;

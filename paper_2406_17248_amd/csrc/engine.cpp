@@ -908,7 +908,35 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
   const std::vector<Pass> passes = plan_passes(plan.prims, n, m, opt.low_qubits);
   const int low_local = std::max(0, std::min(opt.low_qubits, m - 2));
   const int32_t low_mask = (1 << low_local) - 1;
-  for (const Pass& ps : passes) {
+  // Bit layouts between passes: lay[p][q] is the bit of qubit q in the layout pass p reads
+  // (lay[P]: the layout the last pass writes).  Both ends use the natural layout.  With
+  // relayout, pass p writes a layout with pass p+1's tile in its low bits (qubit order),
+  // then the qubits of pass p's tile that pass p+1 lacks, then the rest: pass p+1 reads one
+  // contiguous block per tile, and pass p writes each tile within 2^(m + |T_p - T_p+1|)
+  // amplitudes.  A pass cannot read and write one buffer in two layouts, so passes alternate
+  // between two buffers; with an odd pass count the first pass stays in place.
+  const int P = (int)passes.size();
+  const bool relay = rb && !adjoint && opt.relayout && P >= 2;
+  std::vector<std::vector<int>> lay(P + 1, std::vector<int>(n));
+  for (auto& L : lay)
+    for (int q = 0; q < n; ++q) L[q] = q;
+  if (relay) {
+    for (int p = (P % 2 == 0) ? 1 : 2; p < P; ++p) {
+      const uint64_t next = passes[p].tile_mask, prev = passes[p - 1].tile_mask;
+      int pos = 0;
+      for (int q = 0; q < n; ++q)
+        if (next >> q & 1) lay[p][q] = pos++;
+      for (int q = 0; q < n; ++q)
+        if ((prev >> q & 1) && !(next >> q & 1)) lay[p][q] = pos++;
+      for (int q = 0; q < n; ++q)
+        if (!((prev | next) >> q & 1)) lay[p][q] = pos++;
+    }
+  }
+  bool moved = false;
+  for (int p = 0; p < P; ++p) moved |= lay[p] != lay[p + 1];
+  plan.relayout = relay && moved;  // else every pass runs in place
+  for (int pi = 0; pi < P; ++pi) {
+    const Pass& ps = passes[pi];
     DevPass dp{};
     dp.tile_mask = ps.tile_mask;
     dp.m = ps.m;
@@ -973,29 +1001,55 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
     dp.op_count = (int32_t)plan.ops.size() - dp.op_first;
     if (rb) {
       dp.dep_first = (int32_t)plan.deps.size();
-      auto deposit = [&](uint64_t v) {
-        uint64_t r = 0, m = ps.tile_mask;
-        for (; m && v; v >>= 1, m &= m - 1)
-          if (v & 1) r |= m & (~m + 1);
-        return r;
-      };
-      for (int i = 0; i < 128; ++i) plan.deps.push_back(deposit((uint64_t)i));
-      for (int i = 0; i < 128; ++i) plan.deps.push_back(deposit((uint64_t)i << 7));
-      // contiguous runs of the bits outside the tile, lowest first
-      const uint64_t outside = (n >= 64 ? ~0ull : ((1ull << n) - 1)) & ~ps.tile_mask;
-      std::vector<uint64_t> runs;
-      int shift = 0;
-      for (int q = 0; q < n;) {
-        if (!(outside >> q & 1)) { ++q; continue; }
-        int len = 0;
-        while (q + len < n && (outside >> (q + len) & 1)) ++len;
-        runs.push_back((uint64_t)q | (uint64_t)len << 8 | (uint64_t)shift << 16);
-        shift += len;
-        q += len;
+      const std::vector<int>& Lr = lay[pi];
+      const std::vector<int>& Lw = lay[pi + 1];
+      dp.relayout = Lr != Lw ? 1 : 0;
+      // tile qubits in local-bit order, and the outside qubits in tile-index-bit order
+      std::vector<int> tq, ord;
+      for (int q = 0; q < n; ++q)
+        if (ps.tile_mask >> q & 1) tq.push_back(q);
+      // with relayout, consecutive tiles differ first in the qubits that are low bits of
+      // the layout this pass writes, so their writes fill the same lines; a pass reading
+      // the natural layout with a tile that is not the lowest qubits keeps qubit order
+      const bool reads_natural = Lr == lay[P] && ps.tile_mask != (1ull << ps.m) - 1;
+      const bool store_first = dp.relayout && !reads_natural;
+      if (store_first) {
+        const uint64_t next = passes[pi + 1 < P ? pi + 1 : pi].tile_mask;
+        for (int q = 0; q < n; ++q)
+          if (!(ps.tile_mask >> q & 1) && (next >> q & 1)) ord.push_back(q);
+        for (int q = 0; q < n; ++q)
+          if (!(ps.tile_mask >> q & 1) && !(next >> q & 1)) ord.push_back(q);
+      } else {
+        for (int q = 0; q < n; ++q)
+          if (!(ps.tile_mask >> q & 1)) ord.push_back(q);
       }
-      if ((int)runs.size() + 257 > kDepEntries) fail(QSV_EINVAL, "internal: too many runs of outside bits");
-      plan.deps.push_back(runs.size());
-      plan.deps.insert(plan.deps.end(), runs.begin(), runs.end());
+      auto tables = [&](const std::vector<int>& L) {
+        for (int h = 0; h < 2; ++h)
+          for (int v = 0; v < 128; ++v) {
+            uint64_t r = 0;
+            for (int b = 0; b < 7; ++b)
+              if ((v >> b & 1) && 7 * h + b < (int)tq.size()) r |= 1ull << L[tq[7 * h + b]];
+            plan.deps.push_back(r);
+          }
+      };
+      tables(Lr);
+      tables(Lw);
+      auto runs = [&](const std::vector<int>& L, int at) {
+        std::vector<uint64_t> r;
+        for (size_t i = 0; i < ord.size();) {
+          size_t len = 1;
+          while (i + len < ord.size() && L[ord[i + len]] == L[ord[i]] + (int)len) ++len;
+          r.push_back((uint64_t)L[ord[i]] | (uint64_t)len << 8 | (uint64_t)i << 16);
+          i += len;
+        }
+        if ((int)r.size() > kMaxRuns) fail(QSV_EINVAL, "internal: too many runs of outside bits");
+        plan.deps.resize(dp.dep_first + at, 0);
+        plan.deps.push_back(r.size());
+        plan.deps.insert(plan.deps.end(), r.begin(), r.end());
+      };
+      runs(lay[P], kRunsLogical);  // the natural layout: bit q is qubit q
+      runs(Lr, kRunsLoad);
+      runs(Lw, kRunsStore);
       plan.deps.resize(dp.dep_first + kDepEntries, 0);
     }
     if (rb) {
@@ -1034,8 +1088,8 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
 std::string structure_key(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
   std::string key;
   auto put = [&](const void* p, size_t n) { key.append(reinterpret_cast<const char*>(p), n); };
-  const int32_t head[9] = {c->n_qubits, adjoint ? 1 : 0, opt.tile_qubits, opt.low_qubits, opt.fuse_zz ? 1 : 0,
-                           opt.dtype, opt.use_rb ? 1 : 0, opt.rb_min, opt.reg_bits};
+  const int32_t head[10] = {c->n_qubits, adjoint ? 1 : 0, opt.tile_qubits, opt.low_qubits, opt.fuse_zz ? 1 : 0,
+                            opt.dtype, opt.use_rb ? 1 : 0, opt.rb_min, opt.reg_bits, opt.relayout ? 1 : 0};
   put(head, sizeof(head));
   for (size_t i = 0; i < c->n_gates; ++i) {
     const qsv_gate& g = c->gates[i];

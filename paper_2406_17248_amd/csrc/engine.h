@@ -87,7 +87,8 @@ struct DevPass {
   int32_t  op_first, op_count;
   int32_t  pslot_first, pslot_count;
   int32_t  win_lo, win_n;  // register-blocked: ctab window of the pass's per-lane lookups
-  int32_t  dep_first;      // register-blocked: first of the pass's 256 Plan::deps entries
+  int32_t  dep_first;      // register-blocked: first of the pass's kDepEntries Plan::deps entries
+  int32_t  relayout;       // register-blocked: stores go to another layout (and buffer)
 };
 
 // A fully planned execution (forward or adjoint reverse sweep) of one circuit structure.
@@ -97,11 +98,12 @@ struct Plan {
   int32_t n_qubits = 0;
   std::vector<Prim> prims;
   std::vector<DevPass> passes;
-  // register-blocked passes, kDepEntries per pass: global-index deposits of local indices
-  // (entry i < 128: local bits 0..6 = i; entry 128 + i: local bits 7..13 = i), then the
-  // number of contiguous runs of bits outside the tile and one entry per run,
-  // lo | len << 8 | shift << 16: tile t has base = OR_r ((t >> shift) & (2^len - 1)) << lo
+  // register-blocked passes, kDepEntries per pass (layout in qsv_ops.h): where each local
+  // index is read and written, and runs forming a tile's logical, load and store bases
   std::vector<uint64_t> deps;
+  // forward passes move the state between bit layouts (pass p stores in a layout whose low
+  // bits are pass p+1's tile); the first pass reads and the last writes the natural layout
+  bool relayout = false;
   std::vector<TileOp> ops;
   std::vector<DiagEntry> diag;
   std::vector<ZZEdge> edges;
@@ -122,6 +124,7 @@ struct PlanOptions {
   bool    use_rb = true;      // register-blocked kernel for tiles of rb_min..13 qubits
   int32_t rb_min = 9;         // smallest register-blocked tile (smaller ones idle threads)
   int32_t reg_bits = 3;       // register bits of register-blocked passes (3, or 4 forward)
+  bool    relayout = false;   // forward register-blocked plans: relayout between passes
 };
 
 // Validate a circuit against n_params (and the state's n).  Throws Error.

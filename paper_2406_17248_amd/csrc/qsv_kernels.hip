@@ -566,18 +566,23 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
   const int nloc = 1 << m;
   const bool active = FULL || tid < (nloc >> RB);
   const uint64_t TM = A.tile_mask;
-  // the tile's bits outside the tile mask, from the planner's contiguous runs
-  uint64_t base = 0;
-  {
-    const int nruns = (int)ld(A.dep + 256);
-    for (int r = 0; r < nruns; ++r) {
-      const uint64_t e = ld(A.dep + 257 + r);
+  // The tile's base indices from the planner's runs of tile-index bits: logical (bit q is
+  // qubit q: controls and phases read it) and the indices the pass reads and writes (they
+  // differ from the logical one when passes relayout the state).
+  auto run_base = [&](int at) {
+    uint64_t r = 0;
+    const int nruns = (int)ld(A.dep + at);
+    for (int i = 0; i < nruns; ++i) {
+      const uint64_t e = ld(A.dep + at + 1 + i);
       const int lo = (int)(e & 255), len = (int)((e >> 8) & 255), sh = (int)((e >> 16) & 255);
-      base |= ((tile >> sh) & ((1ull << len) - 1)) << lo;
+      r |= ((tile >> sh) & ((1ull << len) - 1)) << lo;
     }
-  }
+    return r;
+  };
+  const uint64_t base = run_base(kRunsLogical);
 
   C* psi = reinterpret_cast<C*>(A.psi) + (int64_t)b * A.bstride;
+  C* out = A.dst ? reinterpret_cast<C*>(A.dst) + (int64_t)b * A.bstride : psi;
   C* lam = ADJ ? reinterpret_cast<C*>(A.lam) + (int64_t)b * A.bstride : nullptr;
   const C* src = A.src ? reinterpret_cast<const C*>(A.src) + (int64_t)b * A.src_bstride : psi;
   const C* T = reinterpret_cast<const C*>(A.ctab) + (int64_t)b * A.ctab_bstride;
@@ -626,8 +631,9 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
     }
   };
   auto lds_at = [&](int byte_off) -> C& { return *reinterpret_cast<C*>(reinterpret_cast<char*>(buf) + byte_off); };
-  // Global index of a local index: two lookup tables of deposits into the tile mask
-  // (local bits 0..6 and 7..13), computed by the planner for the pass.
+  // Index a local index is read from: two lookup tables of deposits (local bits 0..6 and
+  // 7..13) computed by the planner for the pass; before the stores they are replaced by the
+  // tables of the index it is written to when the pass relayouts.
   __shared__ uint64_t dep_lo[128], dep_hi[128];
   for (int i = tid; i < 128; i += NT) {
     dep_lo[i] = A.dep[i];
@@ -645,9 +651,9 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
   for (int i = tid; i < win_n; i += NT) win[i] = T[win_lo + i];
   __syncthreads();
   auto tab = [&](int off) -> C { return win_n ? win[off - win_lo] : ldc(T + off); };
-  auto globals = [&](uint64_t* xo) {
+  auto globals = [&](uint64_t tile_base, uint64_t* xo) {
 #pragma unroll
-    for (int k = 0; k < NR; ++k) xo[k] = base | dep_lo[jk[k] & 127] | dep_hi[jk[k] >> 7];
+    for (int k = 0; k < NR; ++k) xo[k] = tile_base | dep_lo[jk[k] & 127] | dep_hi[jk[k] >> 7];
   };
   layout(A.lr0, jk);
   int lr_cur = A.lr0;                                  // register bits of the current layout
@@ -656,7 +662,7 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
   C v[NR], w[NR];
   if (active) {
     uint64_t xk[NR];
-    globals(xk);
+    globals(A.relayout ? run_base(kRunsLoad) : base, xk);
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       v[k] = src[xk[k]];
@@ -888,12 +894,22 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
     }
   }
 
+  uint64_t store_base = base;
+  if (A.relayout) {
+    __syncthreads();
+    for (int i = tid; i < 128; i += NT) {
+      dep_lo[i] = A.dep[256 + i];
+      dep_hi[i] = A.dep[384 + i];
+    }
+    __syncthreads();
+    store_base = run_base(kRunsStore);
+  }
   if (active) {
     uint64_t xk[NR];
-    globals(xk);
+    globals(store_base, xk);
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-      psi[xk[k]] = v[k];
+      out[xk[k]] = v[k];
       if (ADJ) lam[xk[k]] = w[k];
     }
   }

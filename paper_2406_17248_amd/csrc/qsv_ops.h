@@ -88,8 +88,15 @@ struct ZZEdge {
   uint64_t omask;
 };
 
-// Planner tables per register-blocked pass: 256 deposits, a run count, up to 63 runs.
-constexpr int kDepEntries = 320;
+// Planner tables per register-blocked pass (entries of 64 bits):
+//   [0, 256)    where local index j is read: entry j & 127 ORed with entry 128 + (j >> 7)
+//   [256, 512)  where local index j is written (the same tables unless the pass relayouts)
+//   kRunsLogical, kRunsLoad, kRunsStore: a run count, then up to kMaxRuns runs
+//               lo | len << 8 | shift << 16, each putting tile-index bits
+//               [shift, shift + len) at bits [lo, lo + len) of the tile's base: the logical
+//               base (qubit values, for controls and phases), and the bases read and written
+constexpr int kRunsLogical = 512, kRunsLoad = 544, kRunsStore = 576, kMaxRuns = 31;
+constexpr int kDepEntries = 608;
 
 // Largest ctab window (complex entries) a register-blocked pass stages in LDS.
 constexpr int kMaxWindow = 256;
@@ -98,6 +105,7 @@ struct PassArgs {
   void*        psi;           // state(s), batch item b at psi + b * bstride amplitudes
   void*        lam;           // adjoint: costate(s), same layout
   const void*  src;           // first forward pass: read from src (+ b * src_bstride)
+  void*        dst;           // written instead of psi when not null (relayouting passes)
   int64_t      bstride;
   int64_t      src_bstride;
   const TileOp*    ops;
@@ -119,7 +127,7 @@ struct PassArgs {
   int64_t      n_tiles;       // tiles of this state (column length of partials)
   int64_t      win_lo;
   int32_t      pass_pslots;   // adjoint: gradient slots (pslot values) used by this pass
-  int32_t      pad1;
+  int32_t      relayout;      // 1: stores use their own tables and base (see kDepEntries)
 };
 
 // Adjoint register-blocked passes keep each gradient slot's per-wave sums in LDS until the

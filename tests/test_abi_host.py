@@ -100,3 +100,23 @@ def test_brick_plan_pass_count():
     circ, _ = W.brick_workload()
     _, _, n_passes, _ = L.qsv_plan_debug(circ, 13)
     assert n_passes <= 24
+
+
+def test_relayout_plans_follow_every_amplitude(tmp_path):
+    """The planner's relayouting forward plans, checked on the host through their address
+    tables (tests/host/relayout_check.cpp, built here with g++ against the planner): every
+    pass reads each amplitude where the previous pass wrote it, writes a permutation of the
+    state, and the last pass leaves the natural layout."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "relayout_check")
+    src = os.path.join(ROOT, "tests", "host", "relayout_check.cpp")
+    csrc = os.path.join(ROOT, "paper_2406_17248_amd", "csrc")
+    subprocess.run([gxx, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", csrc, src,
+                    os.path.join(csrc, "engine.cpp"), "-o", exe], check=True)
+    res = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert res.returncode == 0, res.stdout[-2000:]
+    assert "relayouting plans" in res.stdout

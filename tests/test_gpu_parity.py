@@ -63,6 +63,30 @@ def test_apply_circuit_matches_oracle(Q, dtype, n, tile, seed):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,tile,seed", [(20, 9, 31), (19, 10, 32), (21, 11, 33), (18, 9, 34), (22, 12, 35)])
+def test_relayout_passes_match_in_place(Q, dtype, n, tile, seed):
+    """Fused passes that store each tile in the next pass's bit layout (alternating between
+    the state and a scratch buffer; even and odd pass counts) give the same amplitudes, bit
+    for bit, as in-place passes, and both match the oracle."""
+    print(f"relayout n={n} tile={tile} seed={seed} dtype={dtype}", flush=True)
+    circ = W.random_circuit(n, 200, seed, max_ctrls=2)
+    params = np.random.default_rng(seed).uniform(-np.pi, np.pi, 8)
+    psi0 = W.random_state(n, np.random.default_rng(seed + 1000))
+    psi0 = psi0.astype(np.complex64 if dtype == "c64" else np.complex128)
+    ref = O.simulate(circ, params, psi0.astype(np.complex128))
+    got = {}
+    for relayout in (1, 0):
+        s = _new_state(Q, n, dtype, psi0, tile=tile)
+        Q.qsv_state_set_option(s, Q.OPT_RELAYOUT, relayout)
+        Q.qsv_apply_circuit(s, circ, params)
+        Q.qsv_apply_circuit(s, circ, params)  # a second call reuses the scratch buffer
+        got[relayout] = Q.qsv_state_get(s)
+    ref = O.simulate(circ, params, ref)
+    assert np.array_equal(got[0], got[1])
+    assert np.max(np.abs(got[1] - ref)) <= 2 * TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_apply_from_zero_state_and_reset(Q, dtype):
     n = 6
     gs = [W.gate("H", (0,))] + [W.gate("X", (q + 1,), ctrls=(q,)) for q in range(n - 1)]
