@@ -13,8 +13,10 @@ Conventions (MindSpore Quantum paper, section 2):
 * fixed gates I, X, Y, Z, H as printed in section 2.3 (fixed gates);
 * RX/RY/RZ(theta) = exp(-i theta P / 2) as printed in section 2.3
   (parameterized gates);
-* S, T, their inverses, PhaseShift, SWAP, RXX/RYY/RZZ and U3 are the standard
+* S, T, their inverses, PhaseShift, SWAP and RXX/RYY/RZZ are the standard
   definitions (the paper uses them by name without printing the matrices);
+* U3(a, b, c) = RZ(b) RX(-pi/2) RZ(a) RX(pi/2) RZ(c), the decomposition section 4.1
+  (learning a rotation) gives for it, taken as its definition;
 * expectation E = <psi|H|psi> of a Pauli sum (section 2.6, get_expectation);
 * adjoint-method gradient (named in section 7, QAOA task) following Jones &
   Gacon, arXiv:2009.02823; parameter-shift and central finite differences as
@@ -57,19 +59,22 @@ def _pauli_rotation_deriv(P, theta):
 
 
 def _u3(theta, phi, lam):
-    """Standard U3; equal, up to a global phase, to RZ(phi) RY(theta) RZ(lam), the
-    single-qubit rotation of section 4.1 (learning a rotation)."""
+    """U3 as section 4.1 defines it: the rotation RZ(phi) RX(-pi/2) RZ(theta) RX(pi/2)
+    RZ(lam), in which the middle three factors equal RY(theta), written out in closed form
+    (no global phase factor beyond the one this product carries)."""
     c, s = np.cos(theta / 2.0), np.sin(theta / 2.0)
-    return np.array([[c, -np.exp(1j * lam) * s],
-                     [np.exp(1j * phi) * s, np.exp(1j * (phi + lam)) * c]], dtype=np.complex128)
+    ep, em = np.exp(0.5j * (phi + lam)), np.exp(0.5j * (phi - lam))
+    return np.array([[c / ep, -s / em],
+                     [em * s, ep * c]], dtype=np.complex128)
 
 
 def _u3_derivs(theta, phi, lam):
+    """Derivatives of the section 4.1 U3 with respect to theta, phi and lam."""
     c, s = np.cos(theta / 2.0), np.sin(theta / 2.0)
-    el, ep, epl = np.exp(1j * lam), np.exp(1j * phi), np.exp(1j * (phi + lam))
-    d_theta = 0.5 * np.array([[-s, -el * c], [ep * c, -epl * s]], dtype=np.complex128)
-    d_phi = np.array([[0, 0], [1j * ep * s, 1j * epl * c]], dtype=np.complex128)
-    d_lam = np.array([[0, -1j * el * s], [0, 1j * epl * c]], dtype=np.complex128)
+    ep, em = np.exp(0.5j * (phi + lam)), np.exp(0.5j * (phi - lam))
+    d_theta = 0.5 * np.array([[-s / ep, -c / em], [em * c, -ep * s]], dtype=np.complex128)
+    d_phi = 0.5j * np.array([[-c / ep, s / em], [em * s, ep * c]], dtype=np.complex128)
+    d_lam = 0.5j * np.array([[-c / ep, -s / em], [-em * s, ep * c]], dtype=np.complex128)
     return d_theta, d_phi, d_lam
 
 

@@ -212,8 +212,10 @@ def test_qaoa_p1_general_graph_closed_form(graph_seed):
 # Invariants tying the remaining gates to the pinned ones
 # ------------------------------------------------------------------------------------
 def test_u3_matches_section_4_1_decomposition():
-    """Section 4.1: U3(a, b, c) = RZ(b) RX(-pi/2) RZ(a) RX(pi/2) RZ(c), up to a global
-    phase of modulus one."""
+    """Section 4.1 (learning a rotation): U3(a, b, c) = RZ(b) RX(-pi/2) RZ(a) RX(pi/2) RZ(c),
+    exactly (the global phase included, which the general form <phi|U_l^dag H U_r|psi>
+    sees).  The right side is built from the rotations pinned by the printed section 2.6
+    examples; special cases: U3(a, 0, 0) = RY(a), U3(0, b, c) = RZ(b + c)."""
     rng = np.random.default_rng(5)
     for _ in range(5):
         a, b, c = rng.uniform(-np.pi, np.pi, 3)
@@ -221,9 +223,34 @@ def test_u3_matches_section_4_1_decomposition():
               _gate("RZ", 0, angles=(a,)), _gate("RX", 0, angles=(-np.pi / 2,)), _gate("RZ", 0, angles=(b,))]
         V = O.full_circuit_unitary(W.circuit(1, gs))
         U = O.full_circuit_unitary(W.circuit(1, [_gate("U3", 0, angles=(a, b, c))]))
-        ph = V[0, 0] / U[0, 0] if abs(U[0, 0]) > 1e-6 else V[1, 0] / U[1, 0]
-        assert abs(abs(ph) - 1) < 1e-13
-        assert np.allclose(V, ph * U, atol=1e-13)
+        assert np.allclose(V, U, atol=1e-14)
+        RY = O.full_circuit_unitary(W.circuit(1, [_gate("RY", 0, angles=(a,))]))
+        assert np.allclose(O.full_circuit_unitary(W.circuit(1, [_gate("U3", 0, angles=(a, 0.0, 0.0))])), RY,
+                           atol=1e-15)
+        RZ = O.full_circuit_unitary(W.circuit(1, [_gate("RZ", 0, angles=(b + c,))]))
+        assert np.allclose(O.full_circuit_unitary(W.circuit(1, [_gate("U3", 0, angles=(0.0, b, c))])), RZ,
+                           atol=1e-15)
+
+
+def test_u3_ansatz_printed_expectation_and_gradient():
+    """Section 4.1 (learning a rotation): for the U3 ansatz on |0> and H = X0 the printed
+    output is f = -0.04602095 and, in the parameter order (c, a, b) of the listing,
+    g = (-1.17e-17, -3.47310364e-02, -7.96875999e-01), at random p0 not printed.  Since
+    <X> = sin(a) cos(b) here, the printed numbers fix cos(b) up to sign, sin(a) and cos(a);
+    the oracle's E and adjoint gradient at one such point must give all three back."""
+    f, gc, ga, gb = -0.04602095, -1.17340357e-17, -3.47310364e-02, -7.96875999e-01
+    cb = np.hypot(f, ga)                   # |cos b| from sin a cos b and cos a cos b
+    a = np.arctan2(f / cb, ga / cb)
+    b = np.arctan2(gb / -np.sin(a), cb)    # dE/db = -sin a sin b
+    c = 0.6180339887
+    rz = [W.gate("RZ", (0,), params=(W.param_angle(i),)) for i in range(3)]  # c, a, b
+    gs = [rz[0], _gate("RX", 0, angles=(np.pi / 2,)), rz[1], _gate("RX", 0, angles=(-np.pi / 2,)), rz[2]]
+    H = [(1.0, ((0, "X"),))]
+    for circ in (W.circuit(1, gs),
+                 W.circuit(1, [W.gate("U3", (0,), params=(W.param_angle(1), W.param_angle(2), W.param_angle(0)))])):
+        E, g = O.grad_adjoint(circ, H, np.array([c, a, b]))
+        assert abs(E - f) < 1e-8
+        assert np.max(np.abs(g - np.array([gc, ga, gb]))) < 1e-8
 
 
 def test_phase_gates_relations():
