@@ -57,9 +57,9 @@ typedef enum { QSV_C64 = 0, QSV_C128 = 1 } qsv_dtype;
  * Rotations (one angle): RX, RY, RZ = exp(-i theta P / 2) (section 2.3);
  * RXX, RYY, RZZ = exp(-i theta P(x)P / 2) on targets[0], targets[1];
  * PS (phase shift) = diag(1, e^{i theta}).
- * U3 (three angles theta, phi, lambda) = [[cos t/2, -e^{i l} sin t/2],
- *                                         [e^{i p} sin t/2, e^{i(p+l)} cos t/2]],
- * which equals the section 4.1 rotation RZ(phi) RY(theta) RZ(lambda) up to a global phase.
+ * U3 (three angles theta, phi, lambda) = RZ(phi) RX(-pi/2) RZ(theta) RX(pi/2) RZ(lambda)
+ *   = RZ(phi) RY(theta) RZ(lambda) as section 4.1 defines it, global phase included:
+ *   [[e^{-i(p+l)/2} cos t/2, -e^{-i(p-l)/2} sin t/2], [e^{i(p-l)/2} sin t/2, e^{i(p+l)/2} cos t/2]].
  * MAT1 / MAT2: explicit 2x2 / 4x4 complex matrix (section 2.3, custom gates).
  * Any kind may carry controls (ctrl_mask); CNOT is X with one control, CZ is Z with one
  * control.  For 2-qubit kinds, bit b of a matrix row/column index refers to targets[b]. */
@@ -131,8 +131,14 @@ int qsv_state_create(int32_t n_qubits, int32_t dtype, qsv_state** out);
 int qsv_state_wrap(void* device_ptr, int32_t n_qubits, int32_t dtype, qsv_state** out);
 /* Free the state, its workspaces and (if owned) its amplitude buffer.  NULL is a no-op. */
 int qsv_state_destroy(qsv_state* s);
-/* Queue all further work of this state on the given hipStream_t (NULL: null stream). */
+/* Queue all further work of this state on the given hipStream_t (NULL: null stream).
+ * Work already queued on the previous stream is not waited for: order it first (e.g.
+ * qsv_state_synchronize) when switching streams. */
 int qsv_state_set_stream(qsv_state* s, void* hip_stream);
+/* Free the state's device workspaces (batch states, costates, partial sums, the relayout
+ * buffer; not the amplitudes).  They are allocated again, grow-only, by later calls that need
+ * them.  Waits for the state's stream first. */
+int qsv_state_release_workspace(qsv_state* s);
 /* Wait for all queued work of this state. */
 int qsv_state_synchronize(qsv_state* s);
 /* Basic queries. */
@@ -159,13 +165,18 @@ enum qsv_option {
   QSV_OPT_PROFILE = 3,       /* 1: time every kernel launch with HIP events on the state's
                                 stream (read with qsv_profile_read); 0: off (default) */
   QSV_OPT_RELAYOUT = 4,      /* 1 (default): qsv_apply_circuit runs fused passes out of place
-                                between the state and a scratch buffer of the same size
-                                (allocated on first use, freed with the state), storing each
-                                pass in a bit layout whose low bits are the next pass's tile so
-                                that every pass after the first reads contiguous blocks; the
-                                state is back in the natural layout when the call returns.
-                                Falls back to in-place passes if the scratch buffer cannot be
-                                allocated.  0: always in place */
+                                between the state and a scratch buffer of the same size as the
+                                state (2^n amplitudes: 16 GiB for 30 qubits in complex128),
+                                storing each pass in a bit layout whose low bits are the next
+                                pass's tile so that every pass after the first reads contiguous
+                                blocks; the state is back in the natural layout when the call
+                                returns.  The buffer is allocated with hipMalloc on the first
+                                multi-pass call (also for wrapped states: outside the caller's
+                                allocator) and kept until qsv_state_release_workspace or
+                                qsv_state_destroy.  It is allocated only while at least 1/8 of
+                                its size plus 256 MiB of device memory would stay free; otherwise,
+                                or if the allocation fails, the passes run in place (same
+                                results).  0: always in place, no buffer */
   QSV_OPT_COUNT = 5
 };
 int qsv_state_set_option(qsv_state* s, int32_t option, int64_t value);
@@ -205,8 +216,11 @@ int qsv_expectation_and_grad_batch(qsv_state* s, const qsv_circuit* c, const qsv
  * the adjoint reverse sweep over those states, holding only psi and lambda per batch item,
  * and returns out_grad[b][p] = dE_weights[b] * dE_b / dparams[b][p] (a vector-Jacobian
  * product).  If the kept states do not match the call (different circuit, Hamiltonian,
- * parameters or batch, or another call used the workspace in between) the forward sweep
- * is recomputed first, so the result never depends on call order. */
+ * parameters or batch, another call used the workspace in between, or an entry point of
+ * this library wrote the start state since: qsv_state_set / reset / copy, qsv_apply_circuit,
+ * qsv_apply_pauli_sum) the forward sweep is recomputed first, so the result does not depend
+ * on call order.  Writes to a wrapped state's memory made outside this library are not
+ * seen: after such a write, call qsv_forward_batch again before qsv_backward_batch. */
 int qsv_forward_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h,
                       const double* params, size_t batch, size_t n_params, double* out_E);
 int qsv_backward_batch(qsv_state* s, const qsv_circuit* c, const qsv_pauli_sum* h,

@@ -29,6 +29,7 @@ GATE_KIND = {
 EXPORTED = (
     "qsv_status_string", "qsv_last_error", "qsv_version",
     "qsv_state_create", "qsv_state_wrap", "qsv_state_destroy", "qsv_state_set_stream",
+    "qsv_state_release_workspace",
     "qsv_state_synchronize", "qsv_state_info", "qsv_state_reset", "qsv_state_set", "qsv_state_get",
     "qsv_state_copy", "qsv_state_set_option", "qsv_state_get_option",
     "qsv_apply_circuit", "qsv_expectation", "qsv_apply_pauli_sum",
@@ -103,6 +104,7 @@ def lib():
             "qsv_state_wrap": ([vp, i32, i32, C.POINTER(vp)], C.c_int),
             "qsv_state_destroy": ([vp], C.c_int),
             "qsv_state_set_stream": ([vp, vp], C.c_int),
+            "qsv_state_release_workspace": ([vp], C.c_int),
             "qsv_state_synchronize": ([vp], C.c_int),
             "qsv_state_info": ([vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(vp)], C.c_int),
             "qsv_state_reset": ([vp], C.c_int),
@@ -304,6 +306,10 @@ def qsv_state_destroy(s):
 
 def qsv_state_set_stream(s, stream_ptr):
     check(lib().qsv_state_set_stream(s.handle, C.c_void_p(stream_ptr)))
+
+
+def qsv_state_release_workspace(s):
+    check(lib().qsv_state_release_workspace(s.handle))
 
 
 def qsv_state_synchronize(s):

@@ -53,8 +53,10 @@ struct qsv_state {
   size_t stage_bytes = 0;
   hipEvent_t stage_ev = nullptr;
   bool stage_pending = false;
-  // identity of the evolved states left in ws_psi by qsv_forward_batch ("" if none)
+  // identity of the evolved states left in ws_psi by qsv_forward_batch ("" if none); it
+  // includes `generation`, which every entry point that writes the amplitudes bumps
   std::string fwd_token;
+  uint64_t generation = 0;
   std::unordered_map<std::string, std::unique_ptr<Plan>> plans;
 
   size_t amp_bytes() const { return dtype == QSV_C64 ? 8 : 16; }
@@ -129,36 +131,15 @@ void stage_release_after_queue(qsv_state* s) {
 
 // Default options per dtype.
 void default_options(qsv_state* s) {
-  // measured on the 30-qubit brick circuit (forward) and the 24-qubit QAOA batch (adjoint):
-  // tiles wider than these save passes but need more REMAPs per pass
-  s->opt[QSV_OPT_TILE_QUBITS] = s->dtype == QSV_C64 ? 12 : 11;
-  s->opt[QSV_OPT_ADJ_TILE_QUBITS] = s->dtype == QSV_C64 ? 10 : 11;
+  s->opt[QSV_OPT_TILE_QUBITS] = default_tile_qubits(s->dtype);
+  s->opt[QSV_OPT_ADJ_TILE_QUBITS] = default_adj_tile_qubits(s->dtype);
   s->opt[QSV_OPT_THREADS] = 512;
   s->opt[QSV_OPT_RELAYOUT] = 1;
 }
 
 PlanOptions plan_options(const qsv_state* s, bool adjoint, bool fuse_zz, bool relayout = false) {
-  PlanOptions o;
-  o.relayout = relayout && !adjoint;
-  o.tile_qubits = (int32_t)(adjoint ? s->opt[QSV_OPT_ADJ_TILE_QUBITS] : s->opt[QSV_OPT_TILE_QUBITS]);
-  if (adjoint && o.tile_qubits == 0) o.tile_qubits = s->dtype == QSV_C64 ? 10 : 11;
-  // complex128 adjoint tiles above 12 qubits would spill registers at 1024 threads
-  if (adjoint && s->dtype == QSV_C128) o.tile_qubits = std::min(o.tile_qubits, 12);
-  // tiles below the register-blocked range use the LDS-sweep kernel, whose adjoint
-  // variant stages psi and lambda together
-  if (std::min<int>(o.tile_qubits, s->n) < o.rb_min || rb_capacity_host(s->dtype, std::min<int>(o.tile_qubits, s->n)) < 0)
-    o.tile_qubits = std::min<int>(o.tile_qubits, adjoint ? (s->dtype == QSV_C64 ? 12 : 11) : 13);
-  // qubits every tile keeps for dense global accesses: measured on the 30-qubit brick and
-  // the 24-qubit QAOA batch (with XCD-ordered tiles, neighbouring tiles share cache lines
-  // in one XCD's L2, so keeping only the lowest qubits costs less than the passes it saves;
-  // complex64 forward passes keep two, below which partial-line writes grow by 40 %)
-  o.low_qubits = adjoint ? (s->dtype == QSV_C128 ? 3 : 1) : (s->dtype == QSV_C64 ? 2 : 1);
-  o.fuse_zz = fuse_zz;
-  o.dtype = s->dtype;
-  // complex64 forward passes keep 16 amplitudes per thread (registers still allow 4 waves
-  // per SIMD): fewer REMAPs and half the per-op and per-tile work per amplitude
-  if (!adjoint && s->dtype == QSV_C64) o.reg_bits = 4;
-  return o;
+  return state_plan_options(s->dtype, s->n, (int32_t)s->opt[QSV_OPT_TILE_QUBITS],
+                            (int32_t)s->opt[QSV_OPT_ADJ_TILE_QUBITS], adjoint, fuse_zz, relayout);
 }
 
 const Plan& get_plan(qsv_state* s, const qsv_circuit* c, bool adjoint, bool fuse_zz, bool relayout = false) {
@@ -564,6 +545,23 @@ int qsv_state_destroy(qsv_state* s) {
   });
 }
 
+int qsv_state_release_workspace(qsv_state* s) {
+  return guarded([&] {
+    check_state(s);
+    set_device(s);
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    s->fwd_token.clear();
+    s->ws_psi.release();
+    s->ws_lam.release();
+    s->ws_aux1.release();
+    s->ws_aux2.release();
+    s->partials.release();
+    s->gpart.release();
+    s->relay.release();
+    s->relay_failed = false;
+  });
+}
+
 int qsv_state_set_stream(qsv_state* s, void* hip_stream) {
   return guarded([&] {
     check_state(s);
@@ -592,6 +590,7 @@ int qsv_state_reset(qsv_state* s) {
   return guarded([&] {
     check_state(s);
     set_device(s);
+    ++s->generation;
     timed(s, QSV_K_OTHER, (double)s->namps() * (double)s->amp_bytes(),
           [&] { return launch_set_basis(s->dtype, s->psi, 0, 1, s->n, 0, s->stream); }, "reset");
   });
@@ -603,6 +602,7 @@ int qsv_state_set(qsv_state* s, const void* host_amps, size_t n_amps) {
     if (!host_amps) fail(QSV_EINVAL, "host_amps is NULL");
     if (n_amps != s->namps()) fail(QSV_EINVAL, "n_amps must be 2^n_qubits");
     set_device(s);
+    ++s->generation;
     hip_check(hipMemcpyAsync(s->psi, host_amps, n_amps * s->amp_bytes(), hipMemcpyHostToDevice, s->stream),
               "set state");
     hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
@@ -629,6 +629,7 @@ int qsv_state_copy(qsv_state* dst, const qsv_state* src) {
     if (dst->n != src->n) fail(QSV_EINVAL, "n_qubits mismatch");
     if (dst == src) return;
     set_device(dst);
+    ++dst->generation;
     timed(dst, QSV_K_OTHER, 2.0 * (double)dst->namps() * (double)dst->amp_bytes(),
           [&] { return launch_broadcast_state(dst->dtype, dst->psi, 0, 1, src->psi, dst->n, dst->stream); },
           "copy state");
@@ -668,6 +669,7 @@ int qsv_apply_circuit(qsv_state* s, const qsv_circuit* c, const double* params, 
     check_state(s);
     validate_circuit(c, params ? n_params : 0, s->n);
     set_device(s);
+    ++s->generation;
     bool relay = s->opt[QSV_OPT_RELAYOUT] != 0 && !s->relay_failed;
     if (relay) {
       // relayout only pays when the plan has several register-blocked passes
@@ -676,8 +678,13 @@ int qsv_apply_circuit(qsv_state* s, const qsv_circuit* c, const double* params, 
       const size_t need = s->namps() * s->amp_bytes();
       if (relay && s->relay.bytes < need) {
         s->relay.release();
+        // keep head room for the tables and partial sums of later calls: relayout is an
+        // optimization, in-place passes give the same result
+        size_t free_b = 0, total_b = 0;
+        hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+        const size_t headroom = need / 8 + ((size_t)256 << 20);
         void* ptr = nullptr;
-        if (hipMalloc(&ptr, need) == hipSuccess) {
+        if (free_b >= need + headroom && hipMalloc(&ptr, need) == hipSuccess) {
           s->relay.p = ptr;
           s->relay.bytes = need;
         } else {
@@ -726,6 +733,7 @@ int qsv_apply_pauli_sum(qsv_state* dst, const qsv_state* src, const qsv_pauli_su
     if (dst->n != src->n) fail(QSV_EINVAL, "n_qubits mismatch");
     validate_pauli_sum(h, dst->n);
     set_device(dst);
+    ++dst->generation;
     DevPauli dp = upload_pauli(dst, h, dst->pauli);
     const int G = (int)dp.groups.size();
     dst->outbuf.reserve((2 * G + 1) * sizeof(double));
@@ -802,6 +810,7 @@ static std::string forward_token(const qsv_state* s, const qsv_circuit* c, const
   put(params, batch * n_params * sizeof(double));
   put(&batch, sizeof(batch));
   put(&s->psi, sizeof(void*));
+  put(&s->generation, sizeof(s->generation));
   return t;
 }
 

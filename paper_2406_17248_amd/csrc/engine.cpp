@@ -133,11 +133,13 @@ int gate_numbers(const qsv_circuit* c, const qsv_gate& g, const double* ang, cpl
       out[0] = std::polar(1.0, -h); out[1] = std::polar(1.0, h); out[2] = std::polar(1.0, h); out[3] = std::polar(1.0, -h);
       return 4;
     case QSV_GATE_U3: {
+      // section 4.1: U3(theta, phi, lam) = RZ(phi) RY(theta) RZ(lam), global phase included
       const double th = ang[0], ph = ang[1], la = ang[2];
-      out[0] = std::cos(th / 2);
-      out[1] = -std::polar(1.0, la) * std::sin(th / 2);
-      out[2] = std::polar(1.0, ph) * std::sin(th / 2);
-      out[3] = std::polar(1.0, ph + la) * std::cos(th / 2);
+      const double c = std::cos(th / 2), s = std::sin(th / 2);
+      out[0] = std::polar(c, -(ph + la) / 2);
+      out[1] = std::polar(-s, -(ph - la) / 2);
+      out[2] = std::polar(s, (ph - la) / 2);
+      out[3] = std::polar(c, (ph + la) / 2);
       return 4;
     }
     case QSV_GATE_SWAP:
@@ -182,7 +184,6 @@ int prim_numbers(const Prim& p, const qsv_circuit* c, const double* ang, cplx* o
       out[0] = std::cos(a / 2); out[1] = -std::sin(a / 2); out[2] = std::sin(a / 2); out[3] = std::cos(a / 2);
       cnt = 4;
       break;
-    case M_CPHASE_HALF: out[0] = std::polar(1.0, a / 2); out[1] = out[0]; cnt = 2; break;
     case M_H: {
       const double r = std::sqrt(0.5);
       out[0] = r; out[1] = r; out[2] = r; out[3] = -r; cnt = 4;
@@ -213,7 +214,6 @@ int prim_gen(const Prim& p, cplx* out) {
     case G_Y: out[0] = 0; out[1] = -I1 * k; out[2] = I1 * k; out[3] = 0; return 4;
     case G_Z: out[0] = k; out[1] = -k; return 2;
     case G_PS: out[0] = 0; out[1] = -2 * k; return 2;
-    case G_CPHASE: out[0] = -2 * k; out[1] = -2 * k; return 2;
     case G_ZZ: out[0] = k; out[1] = -k; out[2] = -k; out[3] = k; return 4;
     case G_XX: case G_YY:
       for (int i = 0; i < 16; ++i) out[i] = 0;
@@ -238,6 +238,35 @@ int prim_size(const Prim& p) {
 }
 
 }  // namespace
+
+// ---- options ----------------------------------------------------------------------------------
+int32_t default_tile_qubits(int32_t dtype) { return dtype == QSV_C64 ? 12 : 11; }
+int32_t default_adj_tile_qubits(int32_t dtype) { return dtype == QSV_C64 ? 10 : 11; }
+
+PlanOptions state_plan_options(int32_t dtype, int32_t n, int32_t tile, int32_t adj_tile, bool adjoint, bool fuse_zz,
+                               bool relayout) {
+  PlanOptions o;
+  o.relayout = relayout && !adjoint;
+  o.tile_qubits = adjoint ? adj_tile : tile;
+  if (adjoint && o.tile_qubits == 0) o.tile_qubits = default_adj_tile_qubits(dtype);
+  // complex128 adjoint tiles above 12 qubits would spill registers at 1024 threads
+  if (adjoint && dtype == QSV_C128) o.tile_qubits = std::min(o.tile_qubits, 12);
+  // tiles below the register-blocked range use the LDS-sweep kernel, whose adjoint
+  // variant stages psi and lambda together
+  if (std::min<int>(o.tile_qubits, n) < o.rb_min || rb_capacity_host(dtype, std::min<int>(o.tile_qubits, n)) < 0)
+    o.tile_qubits = std::min<int>(o.tile_qubits, adjoint ? (dtype == QSV_C64 ? 12 : 11) : 13);
+  // qubits every tile keeps for dense global accesses: measured on the 30-qubit brick and
+  // the 24-qubit QAOA batch (with XCD-ordered tiles, neighbouring tiles share cache lines
+  // in one XCD's L2, so keeping only the lowest qubits costs less than the passes it saves;
+  // complex64 forward passes keep two, below which partial-line writes grow by 40 %)
+  o.low_qubits = adjoint ? (dtype == QSV_C128 ? 3 : 1) : (dtype == QSV_C64 ? 2 : 1);
+  o.fuse_zz = fuse_zz;
+  o.dtype = dtype;
+  // complex64 forward passes keep 16 amplitudes per thread (registers still allow 4 waves
+  // per SIMD): fewer REMAPs and half the per-op and per-tile work per amplitude
+  if (!adjoint && dtype == QSV_C64) o.reg_bits = 4;
+  return o;
+}
 
 // ---- validation -----------------------------------------------------------------------------
 void validate_circuit(const qsv_circuit* c, size_t n_params, int32_t n_state) {
@@ -349,17 +378,13 @@ std::vector<Prim> lower_adjoint(const qsv_circuit* c) {
     const bool any_param = g.kind == QSV_GATE_U3 &&
                            (g.param_index[0] >= 0 || g.param_index[1] >= 0 || g.param_index[2] >= 0);
     if (any_param) {
-      // U3 = e^{i(phi+lam)/2} RZ(phi) RY(theta) RZ(lam); the phase is exp(i (phi/2) Pi_c)
-      // exp(i (lam/2) Pi_c) with Pi_c the control projector (the identity without controls,
-      // where it still matters for the derivatives of <phi|U_l^dag H U_r|psi>, which is
-      // linear in U_r).  Forward order of the parts:
-      struct Part { int type, recipe, slot, gen; double scale; };
-      std::vector<Part> parts = {{P_DIAG1, M_RZ_ANGLE, 2, G_Z, 1.0},
-                                 {P_DENSE1, M_RY_ANGLE, 0, G_Y, 1.0},
-                                 {P_DIAG1, M_RZ_ANGLE, 1, G_Z, 1.0},
-                                 {P_DIAG1, M_CPHASE_HALF, 1, G_CPHASE, 0.5},
-                                 {P_DIAG1, M_CPHASE_HALF, 2, G_CPHASE, 0.5}};
-      for (int k = (int)parts.size() - 1; k >= 0; --k) {
+      // U3 = RZ(phi) RY(theta) RZ(lam) (section 4.1), each part carrying the gate's
+      // controls.  Forward order of the parts:
+      struct Part { int type, recipe, slot, gen; };
+      const Part parts[3] = {{P_DIAG1, M_RZ_ANGLE, 2, G_Z},
+                             {P_DENSE1, M_RY_ANGLE, 0, G_Y},
+                             {P_DIAG1, M_RZ_ANGLE, 1, G_Z}};
+      for (int k = 2; k >= 0; --k) {
         Prim p{};
         p.type = parts[k].type;
         p.gate = i;
@@ -372,7 +397,7 @@ std::vector<Prim> lower_adjoint(const qsv_circuit* c) {
         const int pi = g.param_index[parts[k].slot];
         p.param = pi;
         p.gen = pi >= 0 ? parts[k].gen : G_NONE;
-        p.coeff = pi >= 0 ? parts[k].scale * g.param_coeff[parts[k].slot] : 0.0;
+        p.coeff = pi >= 0 ? g.param_coeff[parts[k].slot] : 0.0;
         finish_masks(p);
         out.push_back(p);
       }

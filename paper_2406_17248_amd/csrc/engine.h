@@ -24,7 +24,6 @@ struct Error {
 enum GenKind : int32_t {
   G_NONE = 0, G_X, G_Y, G_Z, G_XX, G_YY, G_ZZ,
   G_PS,      // diag(0, -2): PhaseShift(theta) = exp(-i theta diag(0,-2) / 2)
-  G_CPHASE,  // -2 on the control subspace (target identity): exp(i beta Pi_c)
 };
 
 // How a primitive's numbers are formed at bind time.
@@ -32,7 +31,6 @@ enum MatRecipe : int32_t {
   M_GATE = 0,    // the gate's own matrix (all angles)
   M_RZ_ANGLE,    // RZ(angle[angle_slot]) - parts of a lowered U3
   M_RY_ANGLE,    // RY(angle[angle_slot])
-  M_CPHASE_HALF, // exp(i angle[angle_slot] / 2) on the control subspace
   M_SIGN,        // no numbers (sign flip)
   M_H,           // Hadamard (basis change of a lowered RXX)
   M_RX_PLUS,     // RX(+pi/2) (basis change of a lowered RYY)
@@ -126,6 +124,16 @@ struct PlanOptions {
   int32_t reg_bits = 3;       // register bits of register-blocked passes (3, or 4 forward)
   bool    relayout = false;   // forward register-blocked plans: relayout between passes
 };
+
+// Default tile widths of forward and adjoint plans, measured on the 30-qubit brick circuit
+// (forward) and the 24-qubit QAOA batch (adjoint): wider tiles save passes but need more
+// REMAPs per pass.
+int32_t default_tile_qubits(int32_t dtype);
+int32_t default_adj_tile_qubits(int32_t dtype);
+// Plan options of a state's forward or adjoint plan, from its dtype, qubit count and tile
+// width options (the one place these rules live, used by the library and the host checks).
+PlanOptions state_plan_options(int32_t dtype, int32_t n, int32_t tile, int32_t adj_tile, bool adjoint, bool fuse_zz,
+                               bool relayout);
 
 // Validate a circuit against n_params (and the state's n).  Throws Error.
 void validate_circuit(const qsv_circuit* c, size_t n_params, int32_t n_state);

@@ -1,0 +1,187 @@
+// Host driver of the planner under AddressSanitizer / UndefinedBehaviorSanitizer (no GPU).
+//
+// Random circuits with every gate kind, up to two controls, shared and fixed angles and
+// explicit matrices are validated, lowered, planned (forward and adjoint, both amplitude
+// types, every tile width from per-gate streaming up to 13 qubits, with and without
+// relayout) and bound; Pauli sums are validated and grouped; invalid circuits must be
+// rejected with QSV_EINVAL / QSV_ERANGE.  The structural facts checked on every plan:
+// every primitive is executed exactly once, each op's table offsets lie inside the bound
+// table, each pass's deposit entries and ops lie inside the plan's arrays.
+// Exit status 0 when every check holds.
+#include <cmath>
+#include <cstdio>
+#include <random>
+#include <vector>
+
+#include "engine.h"
+#include "qsv_ops.h"
+using namespace qsv;
+
+static const int kAngles[QSV_GATE_KIND_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 3, 0, 0, 0};
+static const int kTargets[QSV_GATE_KIND_COUNT] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 1, 2, 1, 2};
+
+struct Circ {
+  std::vector<qsv_gate> gates;
+  std::vector<double> mats;
+  qsv_circuit c{};
+};
+
+static void random_circuit(Circ& k, int n, int n_gates, int n_params, std::mt19937& rng) {
+  std::uniform_int_distribution<int> kind_d(0, QSV_GATE_KIND_COUNT - 1), q_d(0, n - 1), pi_d(0, n_params - 1);
+  std::uniform_real_distribution<double> u(-3.0, 3.0);
+  for (int i = 0; i < n_gates; ++i) {
+    qsv_gate g{};
+    g.kind = kind_d(rng);
+    if (kTargets[g.kind] > n) g.kind = QSV_GATE_H;
+    g.targets[0] = q_d(rng);
+    g.targets[1] = -1;
+    if (kTargets[g.kind] == 2)
+      do g.targets[1] = q_d(rng); while (g.targets[1] == g.targets[0]);
+    uint64_t used = 1ull << g.targets[0];
+    if (g.targets[1] >= 0) used |= 1ull << g.targets[1];
+    const int nc = (int)(rng() % 3);
+    for (int j = 0; j < nc && __builtin_popcountll(used) < n; ++j) {
+      int c;
+      do c = q_d(rng); while (used >> c & 1);
+      used |= 1ull << c;
+      g.ctrl_mask |= 1ull << c;
+    }
+    for (int a = 0; a < 3; ++a) {
+      g.param_index[a] = -1;
+      if (a < kAngles[g.kind]) {
+        if (rng() % 4 != 0) g.param_index[a] = pi_d(rng);
+        g.param_coeff[a] = (rng() % 2) ? 1.0 : -0.5;
+        g.angle_const[a] = u(rng);
+      }
+    }
+    g.matrix_offset = -1;
+    if (g.kind == QSV_GATE_MAT1 || g.kind == QSV_GATE_MAT2) {
+      const int d = g.kind == QSV_GATE_MAT1 ? 2 : 4;
+      g.matrix_offset = (int64_t)(k.mats.size() / 2);
+      const bool diag = rng() % 3 == 0;  // diagonal matrices take the diagonal path
+      for (int r = 0; r < d; ++r)
+        for (int cc = 0; cc < d; ++cc) {
+          k.mats.push_back(diag && r != cc ? 0.0 : u(rng));
+          k.mats.push_back(diag && r != cc ? 0.0 : u(rng));
+        }
+    }
+    k.gates.push_back(g);
+  }
+  k.c = qsv_circuit{n, 0, k.gates.data(), k.gates.size(), k.mats.data(), k.mats.size()};
+}
+
+static int check_plan(const Plan& p, const qsv_circuit& c, const std::vector<double>& params, int& checks) {
+  std::vector<int> seen(p.prims.size(), 0);
+  if (!p.unfused) {
+    for (const DevPass& dp : p.passes) {
+      if (dp.op_first < 0 || dp.op_first + dp.op_count > (int)p.ops.size()) return 1;
+      if (dp.rb && (dp.dep_first < 0 || dp.dep_first + kDepEntries > (int)p.deps.size())) return 2;
+      if (dp.m < 1 || dp.m > c.n_qubits || __builtin_popcountll(dp.tile_mask) != dp.m) return 3;
+    }
+    for (const TileOp& op : p.ops) {
+      if (op.mat >= p.ctab_size || op.gen >= p.ctab_size) return 4;
+      if ((op.type == OP_DIAG && op.first + op.count > (int)p.diag.size()) ||
+          (op.type == OP_ZZ && op.first + op.count > (int)p.edges.size()))
+        return 5;
+    }
+    for (const DiagEntry& d : p.diag)
+      if (d.mat >= p.ctab_size || d.gen >= p.ctab_size) return 6;
+  } else {
+    for (size_t i = 0; i < p.stream_mat.size(); ++i)
+      if (p.stream_mat[i] >= p.ctab_size) return 7;
+  }
+  std::vector<cplx> tab((size_t)p.ctab_size + 1);
+  bind_ctab(p, &c, params.data(), nullptr, 0, tab.data());
+  for (const cplx& v : tab)
+    if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return 8;
+  ++checks;
+  return 0;
+}
+
+int main() {
+  std::mt19937 rng(2406);
+  int bad = 0, checks = 0;
+  try {
+    for (int trial = 0; trial < 60; ++trial) {
+      const int n = 2 + trial % 15;
+      Circ k;
+      random_circuit(k, n, 40 + trial, 5, rng);
+      std::vector<double> params(5);
+      for (double& v : params) v = std::uniform_real_distribution<double>(-3, 3)(rng);
+      validate_circuit(&k.c, params.size(), n);
+      for (int dtype : {QSV_C64, QSV_C128})
+        for (bool adjoint : {false, true})
+          for (int tile : {0, 2, 3, 5, 8, 9, 10, 11, 12, 13}) {
+            if (adjoint && tile == 0) continue;
+            for (bool relayout : {false, true}) {
+              PlanOptions o = state_plan_options(dtype, n, tile, tile, adjoint, true, relayout);
+              const Plan p = build_plan(&k.c, adjoint, o);
+              const int r = check_plan(p, k.c, params, checks);
+              if (r) {
+                printf("trial %d n=%d dtype=%d adjoint=%d tile=%d relayout=%d: check %d failed\n", trial, n, dtype,
+                       (int)adjoint, tile, (int)relayout, r);
+                bad = 1;
+              }
+            }
+          }
+      // Pauli sums
+      std::vector<double> co(12);
+      std::vector<uint64_t> xm(12), zm(12);
+      for (int t = 0; t < 12; ++t) {
+        co[t] = std::uniform_real_distribution<double>(-1, 1)(rng);
+        xm[t] = rng() & ((1ull << n) - 1);
+        zm[t] = rng() & ((1ull << n) - 1);
+      }
+      const qsv_pauli_sum h{co.size(), co.data(), xm.data(), zm.data()};
+      validate_pauli_sum(&h, n);
+      size_t terms = 0;
+      for (const PauliGroup& g : group_pauli_sum(&h)) terms += g.zmasks.size();
+      if (terms != co.size()) {
+        printf("pauli grouping lost terms\n");
+        bad = 1;
+      }
+    }
+    // invalid circuits are rejected before planning
+    auto expect_reject = [&](qsv_gate g, int n, size_t n_params, int status, const char* what) {
+      const double m[32] = {1, 0, 0, 0, 0, 0, 1, 0};
+      const qsv_circuit c{n, 0, &g, 1, m, 8};
+      try {
+        validate_circuit(&c, n_params, n);
+      } catch (const Error& e) {
+        if (e.status == status) return;
+      }
+      printf("not rejected: %s\n", what);
+      bad = 1;
+    };
+    qsv_gate g{};
+    g.kind = QSV_GATE_RX;
+    g.targets[0] = 0;
+    for (int a = 0; a < 3; ++a) g.param_index[a] = -1;
+    qsv_gate t = g;
+    t.targets[0] = 7;
+    expect_reject(t, 3, 0, QSV_EINVAL, "target out of range");
+    t = g;
+    t.ctrl_mask = 1;
+    expect_reject(t, 3, 0, QSV_EINVAL, "control on target");
+    t = g;
+    t.param_index[0] = 4;
+    expect_reject(t, 3, 2, QSV_EINVAL, "parameter index out of range");
+    t = g;
+    t.param_index[1] = 0;
+    expect_reject(t, 3, 2, QSV_EINVAL, "unused angle slot");
+    t = g;
+    t.angle_const[0] = NAN;
+    expect_reject(t, 3, 0, QSV_EINVAL, "non-finite angle");
+    t = g;
+    t.kind = QSV_GATE_MAT2;
+    t.targets[1] = 1;
+    t.matrix_offset = 1;
+    expect_reject(t, 3, 0, QSV_EINVAL, "matrix out of range");
+    expect_reject(g, 40, 0, QSV_ERANGE, "too many qubits");
+  } catch (const Error& e) {
+    printf("planner error %d: %s\n", e.status, e.msg.c_str());
+    return 2;
+  }
+  printf("plans checked: %d\n", checks);
+  return bad || checks < 1000;
+}

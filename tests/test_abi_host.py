@@ -102,21 +102,40 @@ def test_brick_plan_pass_count():
     assert n_passes <= 24
 
 
-def test_relayout_plans_follow_every_amplitude(tmp_path):
-    """The planner's relayouting forward plans, checked on the host through their address
-    tables (tests/host/relayout_check.cpp, built here with g++ against the planner): every
-    pass reads each amplitude where the previous pass wrote it, writes a permutation of the
-    state, and the last pass leaves the natural layout."""
+def _sanitized_host_program(tmp_path, name):
+    """Build tests/host/<name>.cpp against the planner with g++ under AddressSanitizer and
+    UndefinedBehaviorSanitizer (any report aborts the program)."""
     import shutil
     import subprocess
     gxx = shutil.which("g++")
     if gxx is None:
         pytest.skip("g++ not available")
-    exe = str(tmp_path / "relayout_check")
-    src = os.path.join(ROOT, "tests", "host", "relayout_check.cpp")
+    exe = str(tmp_path / name)
+    src = os.path.join(ROOT, "tests", "host", name + ".cpp")
     csrc = os.path.join(ROOT, "paper_2406_17248_amd", "csrc")
-    subprocess.run([gxx, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", csrc, src,
+    subprocess.run([gxx, "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                    "-fno-omit-frame-pointer", "-I", os.path.join(ROOT, "include"), "-I", csrc, src,
                     os.path.join(csrc, "engine.cpp"), "-o", exe], check=True)
-    res = subprocess.run([exe], capture_output=True, text=True, timeout=120)
-    assert res.returncode == 0, res.stdout[-2000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")
+    return subprocess.run([exe], capture_output=True, text=True, timeout=300, env=env)
+
+
+def test_relayout_plans_follow_every_amplitude(tmp_path):
+    """The planner's relayouting forward plans, checked on the host through their address
+    tables (tests/host/relayout_check.cpp, built with sanitizers against the planner):
+    every pass reads each amplitude where the previous pass wrote it, writes a permutation
+    of the state, and the last pass leaves the natural layout; for the 30-qubit depth-20
+    brick circuit with the library's default options (both amplitude types) the same is
+    shown through the single-bit images of each pass's linear address maps."""
+    res = _sanitized_host_program(tmp_path, "relayout_check")
+    assert res.returncode == 0, res.stdout[-2000:] + res.stderr[-4000:]
     assert "relayouting plans" in res.stdout
+    assert "ok linear brick30 complex128" in res.stdout and "ok linear brick30 complex64" in res.stdout
+
+
+def test_planner_under_sanitizers(tmp_path):
+    """Random circuits of every gate kind planned and bound at every tile width, both
+    amplitude types, forward and adjoint (tests/host/planner_fuzz.cpp) with ASan/UBSan."""
+    res = _sanitized_host_program(tmp_path, "planner_fuzz")
+    assert res.returncode == 0, res.stdout[-2000:] + res.stderr[-4000:]
+    assert "plans checked" in res.stdout
