@@ -191,6 +191,20 @@ int qsv_apply_circuit(qsv_state* s, const qsv_circuit* c, const double* params, 
  * *out_im is the rounding-level imaginary part (H is Hermitian); either pointer may be NULL. */
 int qsv_expectation(qsv_state* s, const qsv_pauli_sum* h, double* out_re, double* out_im);
 
+/* qsv_expectation for callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same result from the same kernels,
+ * bit for bit, but every device buffer beyond the state (term tables, per-workgroup partial
+ * sums, reduced columns) is one fixed 4 MiB array compiled into the library, one copy per
+ * GPU, kept until the process ends.  The call allocates no device or pinned host memory
+ * (qsv_expectation grows the state's workspaces and a pinned staging buffer) and records
+ * no profiling events.  Limits: at most 8192 terms and 48 distinct x masks (groups of terms
+ * sharing their X/Y qubits); larger sums return QSV_ERANGE before any device work.  Every
+ * call on one GPU uses that GPU's single array: calls that overlap on one GPU (other host
+ * threads, or states on different streams with work in flight) race and may return wrong
+ * values.  The call synchronizes the state's stream before it returns, so calls made one
+ * after another from one thread are safe. */
+int qsv_expectation_noalloc(qsv_state* s, const qsv_pauli_sum* h, double* out_re, double* out_im);
+
 /* dst <- H src, unnormalized (section 2.6, apply_hamiltonian); dst != src, same n/dtype. */
 int qsv_apply_pauli_sum(qsv_state* dst, const qsv_state* src, const qsv_pauli_sum* h);
 

@@ -40,6 +40,7 @@ EXPORTED = (
     "qsv_batch_expectation_and_grad",
     "qsv_mpnn_create", "qsv_mpnn_destroy", "qsv_mpnn_get_params", "qsv_mpnn_predict", "qsv_mpnn_loss_and_grad",
     "qsv_mpnn_train_step", "qsv_expectation_general", "qsv_expectation_and_grad_multi",
+    "qsv_expectation_noalloc",
 )
 MPNN_PARAMS, MPNN_NODES, MPNN_OUTPUTS = 9484, 16, 12
 
@@ -115,6 +116,7 @@ def lib():
             "qsv_state_get_option": ([vp, i32, C.POINTER(i64)], C.c_int),
             "qsv_apply_circuit": ([vp, C.POINTER(qsv_circuit), dp, sz], C.c_int),
             "qsv_expectation": ([vp, C.POINTER(qsv_pauli_sum), dp, dp], C.c_int),
+            "qsv_expectation_noalloc": ([vp, C.POINTER(qsv_pauli_sum), dp, dp], C.c_int),
             "qsv_apply_pauli_sum": ([vp, vp, C.POINTER(qsv_pauli_sum)], C.c_int),
             "qsv_expectation_and_grad": ([vp, C.POINTER(qsv_circuit), C.POINTER(qsv_pauli_sum), dp, sz, dp, dp],
                                          C.c_int),
@@ -355,6 +357,13 @@ def qsv_expectation(s, hamiltonian):
     h = _pauli(hamiltonian)
     re, im = C.c_double(), C.c_double()
     check(lib().qsv_expectation(s.handle, h.ptr, C.byref(re), C.byref(im)))
+    return complex(re.value, im.value)
+
+
+def qsv_expectation_noalloc(s, hamiltonian):
+    h = _pauli(hamiltonian)
+    re, im = C.c_double(), C.c_double()
+    check(lib().qsv_expectation_noalloc(s.handle, h.ptr, C.byref(re), C.byref(im)))
     return complex(re.value, im.value)
 
 

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqsv.so")
 
-SOURCES = ["qsv_kernels.hip", "engine.cpp", "api.cpp", "batch.cpp", "mpnn.hip"]
+SOURCES = ["qsv_kernels.hip", "engine.cpp", "api.cpp", "batch.cpp", "mpnn.hip", "noalloc.hip"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

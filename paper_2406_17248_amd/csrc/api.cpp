@@ -13,6 +13,7 @@
 #include "../../include/qsv.h"
 #include "engine.h"
 #include "hip_util.h"
+#include "noalloc.h"
 #include "qsv_kernels.h"
 
 using namespace qsv;
@@ -309,49 +310,68 @@ struct DevPauli {
   std::vector<const double*> cre, cim;
 };
 
-DevPauli upload_pauli(qsv_state* s, const qsv_pauli_sum* h, DevBuf& buf) {
-  DevPauli dp;
-  dp.groups = group_pauli_sum(h);
+// Bytes of the groups' term tables (z masks, coefficient real and imaginary parts, each
+// array `align`-byte aligned).
+size_t pauli_table_bytes(const std::vector<PauliGroup>& groups, size_t align = 256) {
   size_t total = 0;
-  for (auto& g : dp.groups) total += align_up(g.zmasks.size() * 8, 256) * 3;
-  total = total ? total : 256;
-  char* st = static_cast<char*>(stage_acquire(s, total));
+  for (auto& g : groups) total += align_up(g.zmasks.size() * 8, align) * 3;
+  return total;
+}
+
+// Pack the tables into host bytes `host`; the returned pointers are where they sit once
+// the bytes are copied to device address `dev`.
+DevPauli pack_pauli(std::vector<PauliGroup> groups, char* host, char* dev, size_t align = 256) {
+  DevPauli dp;
+  dp.groups = std::move(groups);
   size_t off = 0;
-  std::vector<size_t> offs;
   for (auto& g : dp.groups) {
-    const size_t sz = g.zmasks.size() * 8;
-    offs.push_back(off);
-    std::memcpy(st + off, g.zmasks.data(), sz);
-    off += align_up(sz, 256);
-    std::memcpy(st + off, g.cre.data(), sz);
-    off += align_up(sz, 256);
-    std::memcpy(st + off, g.cim.data(), sz);
-    off += align_up(sz, 256);
+    const size_t sz = g.zmasks.size() * 8, al = align_up(sz, align);
+    std::memcpy(host + off, g.zmasks.data(), sz);
+    std::memcpy(host + off + al, g.cre.data(), sz);
+    std::memcpy(host + off + 2 * al, g.cim.data(), sz);
+    dp.z.push_back(reinterpret_cast<const uint64_t*>(dev + off));
+    dp.cre.push_back(reinterpret_cast<const double*>(dev + off + al));
+    dp.cim.push_back(reinterpret_cast<const double*>(dev + off + 2 * al));
+    off += 3 * al;
   }
+  return dp;
+}
+
+DevPauli upload_pauli(qsv_state* s, const qsv_pauli_sum* h, DevBuf& buf) {
+  std::vector<PauliGroup> groups = group_pauli_sum(h);
+  const size_t bytes = pauli_table_bytes(groups);
+  const size_t total = bytes ? bytes : 256;
+  char* st = static_cast<char*>(stage_acquire(s, total));
   buf.reserve(total);
+  DevPauli dp = pack_pauli(std::move(groups), st, static_cast<char*>(buf.p));
   hip_check(hipMemcpyAsync(buf.p, st, total, hipMemcpyHostToDevice, s->stream), "upload pauli");
   stage_release_after_queue(s);
-  char* d = static_cast<char*>(buf.p);
-  for (size_t i = 0; i < dp.groups.size(); ++i) {
-    const size_t sz = align_up(dp.groups[i].zmasks.size() * 8, 256);
-    dp.z.push_back(reinterpret_cast<const uint64_t*>(d + offs[i]));
-    dp.cre.push_back(reinterpret_cast<const double*>(d + offs[i] + sz));
-    dp.cim.push_back(reinterpret_cast<const double*>(d + offs[i] + 2 * sz));
-  }
   return dp;
 }
 
 // Expectation partials (and optionally lambda = H psi) for batch states; returns the device
 // pointer of reduced columns [batch][2 * groups] in s->outbuf at byte offset out_off.
+// partials: NULL for the state's workspace (all groups at once), or a caller's buffer of
+// 2 * chunk * pauli_blocks(n) doubles that groups reuse `chunk` at a time, each chunk's
+// columns reduced before the next chunk starts (batch 1 only; the same sums in the same
+// order).  untimed: launch without profiling events.
 void run_pauli(qsv_state* s, const DevPauli& dp, const void* psi, void* lam, int64_t bstride, int batch,
-               double* out_cols) {
+               double* out_cols, double* partials = nullptr, int chunk = 0, bool untimed = false) {
   const int G = (int)dp.groups.size();
   const unsigned nblk = pauli_blocks(s->n);
-  const size_t need = (size_t)batch * 2 * G * nblk * sizeof(double);
-  s->partials.reserve(need ? need : 8);
+  if (!partials) {
+    const size_t need = (size_t)batch * 2 * G * nblk * sizeof(double);
+    s->partials.reserve(need ? need : 8);
+    partials = static_cast<double*>(s->partials.p);
+    chunk = G;
+  } else if (chunk < 1 || (batch != 1 && chunk < G)) {
+    fail(QSV_EINVAL, "internal: chunked Pauli partials need batch 1");
+  }
   if (lam && G == 0)
     hip_check(launch_set_basis(s->dtype, lam, bstride, batch, s->n, ~0ull, s->stream), "zero lambda");
-  for (int g = 0; g < G; ++g) {
+  for (int g0 = 0; g0 < G; g0 += chunk) {
+  const int g1 = std::min(G, g0 + chunk), nc = 2 * (g1 - g0);
+  for (int g = g0; g < g1; ++g) {
     PauliGroupArgs A{};
     A.psi = psi;
     A.lam = lam;
@@ -359,22 +379,22 @@ void run_pauli(qsv_state* s, const DevPauli& dp, const void* psi, void* lam, int
     A.zmasks = dp.z[g];
     A.cre = dp.cre[g];
     A.cim = dp.cim[g];
-    A.partials = static_cast<double*>(s->partials.p);
+    A.partials = partials;
     A.xmask = dp.groups[g].xmask;
     A.n_terms = (int32_t)dp.groups[g].zmasks.size();
     A.n_qubits = s->n;
     A.accumulate = g > 0 ? 1 : 0;
-    A.col = 2 * g;
-    A.ncols = 2 * G;
+    A.col = 2 * (g - g0);
+    A.ncols = nc;
     A.real_coeffs = std::all_of(dp.groups[g].cim.begin(), dp.groups[g].cim.end(), [](double c) { return c == 0.0; });
     // read psi; write lambda (and read it when accumulating)
     const double sb = (double)batch * (double)s->namps() * (double)s->amp_bytes();
     const double bytes = sb * (1.0 + (lam ? 1.0 : 0.0) + (lam && g > 0 ? 1.0 : 0.0));
-    timed(s, QSV_K_PAULI, bytes, [&] { return launch_pauli_group(s->dtype, A, batch, s->stream); }, "pauli pass");
+    if (untimed) hip_check(launch_pauli_group(s->dtype, A, batch, s->stream), "pauli pass");
+    else timed(s, QSV_K_PAULI, bytes, [&] { return launch_pauli_group(s->dtype, A, batch, s->stream); }, "pauli pass");
   }
-  hip_check(launch_reduce_columns(static_cast<double*>(s->partials.p), nblk, (int64_t)batch * 2 * G, out_cols,
-                                  s->stream),
-            "reduce");
+  hip_check(launch_reduce_columns(partials, nblk, (int64_t)batch * nc, out_cols + 2 * g0, s->stream), "reduce");
+  }
 }
 
 qsv_state* check_state(const qsv_state* s) {
@@ -719,6 +739,39 @@ int qsv_expectation(qsv_state* s, const qsv_pauli_sum* h, double* out_re, double
     hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     double re = 0, im = 0;
     for (int g = 0; g < G; ++g) { re += host[2 * g]; im += host[2 * g + 1]; }
+    if (out_re) *out_re = re;
+    if (out_im) *out_im = im;
+  });
+}
+
+int qsv_expectation_noalloc(qsv_state* s, const qsv_pauli_sum* h, double* out_re, double* out_im) {
+  return guarded([&] {
+    check_state(s);
+    validate_pauli_sum(h, s->n);
+    if (h->n_terms > kNoallocMaxTerms) fail(QSV_ERANGE, "more Pauli terms than the fixed scratch holds");
+    set_device(s);
+    char* scr = static_cast<char*>(noalloc_scratch());
+    std::vector<PauliGroup> groups = group_pauli_sum(h);
+    const int G = (int)groups.size();
+    double re = 0, im = 0;
+    if (G > 0) {
+      // scratch layout: term tables | reduced columns | partials of kNoallocChunk groups
+      const size_t tab = pauli_table_bytes(groups, 8);
+      const size_t out_off = align_up(tab, 256);
+      const size_t part_off = align_up(out_off + (size_t)2 * G * sizeof(double), 256);
+      const size_t part_bytes = (size_t)2 * kNoallocChunk * pauli_blocks(s->n) * sizeof(double);
+      if (part_off + part_bytes > kNoallocScratchBytes) fail(QSV_ERANGE, "Pauli sum too large for the fixed scratch");
+      std::vector<char> host(tab);
+      DevPauli dp = pack_pauli(std::move(groups), host.data(), scr, 8);
+      hip_check(hipMemcpyAsync(scr, host.data(), tab, hipMemcpyHostToDevice, s->stream), "upload pauli");
+      double* d_out = reinterpret_cast<double*>(scr + out_off);
+      run_pauli(s, dp, s->psi, nullptr, 0, 1, d_out, reinterpret_cast<double*>(scr + part_off), kNoallocChunk, true);
+      std::vector<double> cols((size_t)2 * G);
+      hip_check(hipMemcpyAsync(cols.data(), d_out, (size_t)2 * G * sizeof(double), hipMemcpyDeviceToHost, s->stream),
+                "download");
+      hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+      for (int g = 0; g < G; ++g) { re += cols[2 * g]; im += cols[2 * g + 1]; }
+    }
     if (out_re) *out_re = re;
     if (out_im) *out_im = im;
   });
