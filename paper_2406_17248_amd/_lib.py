@@ -264,6 +264,8 @@ class State:
         self.n_qubits = n_qubits
         self.dtype = dtype
         self._keepalive = keepalive
+        self.stream_ptr = 0        # hipStream_t the state's work is queued on (0: null stream)
+        self.device_index = None   # device of wrapped memory, when known
 
     def __del__(self):
         try:
@@ -308,6 +310,7 @@ def qsv_state_destroy(s):
 
 def qsv_state_set_stream(s, stream_ptr):
     check(lib().qsv_state_set_stream(s.handle, C.c_void_p(stream_ptr)))
+    s.stream_ptr = int(stream_ptr or 0)
 
 
 def qsv_state_release_workspace(s):

@@ -40,7 +40,7 @@ def test_batch_matches_oracle(Q, dtype):
         E_ref, g_ref = O.grad_adjoint(c, h, p)
         tol = TOL[dtype] * _scale(h)
         assert abs(E[i] - E_ref) <= tol, (i, c["n_qubits"])
-        assert np.max(np.abs(g[b.offsets[i]:b.offsets[i + 1]] - g_ref)) <= 10 * tol, (i, c["n_qubits"])
+        assert np.max(np.abs(g[b.offsets[i]:b.offsets[i + 1]] - g_ref)) <= tol, (i, c["n_qubits"])
 
 
 def test_graph_replays_with_eager_work_between(Q):
@@ -59,7 +59,7 @@ def test_graph_replays_with_eager_work_between(Q):
             pi = p[b.offsets[i]:b.offsets[i + 1]]
             E_ref, g_ref = O.grad_adjoint(circs[i], hams[i], pi)
             assert abs(E[i] - E_ref) <= 1e-12 * _scale(hams[i])
-            assert np.max(np.abs(g[b.offsets[i]:b.offsets[i + 1]] - g_ref)) <= 1e-11 * _scale(hams[i])
+            assert np.max(np.abs(g[b.offsets[i]:b.offsets[i + 1]] - g_ref)) <= 1e-12 * _scale(hams[i])
 
 
 def test_autotune_picks_a_candidate_and_keeps_results(Q):
@@ -70,24 +70,33 @@ def test_autotune_picks_a_candidate_and_keeps_results(Q):
     assert t in (10, 11, 12, 13)
     assert b.info()["tile_qubits"] == t
     E1, g1 = Q.qsv_batch_expectation_and_grad(b, params)
-    assert np.max(np.abs(E1 - E0)) < 1e-5 * 20 and np.max(np.abs(g1 - g0)) < 1e-4 * 20
+    S = max(_scale(h) for h in hams)
+    assert np.max(np.abs(E1 - E0)) <= 1e-5 * S and np.max(np.abs(g1 - g0)) <= 1e-5 * S
 
 
 def test_uneven512_workload(Q):
     """512 circuits (8-20 qubits, depth 2-10, 50 Pauli strings each), complex64: every circuit
-    against the per-circuit path, and the smallest ones against the oracle."""
+    against the per-circuit path, and against the oracle the six smallest circuits plus, for
+    every qubit count 8..20, its shallowest circuit."""
     circs, hams, params = W.uneven_batch_workload()
     b = Q.qsv_batch_create(circs, hams, "c64")
     E, g = Q.qsv_batch_expectation_and_grad(b, params)
     assert np.all(np.isfinite(E)) and np.all(np.isfinite(g))
-    order = np.argsort([c["n_qubits"] for c in circs], kind="stable")
+    order = list(np.argsort([c["n_qubits"] for c in circs], kind="stable")[:6])
+    by_n = {}
+    for i, c in enumerate(circs):
+        k = c["n_qubits"]
+        if k not in by_n or len(c["gates"]) < len(circs[by_n[k]]["gates"]):
+            by_n[k] = i
+    order += [i for k, i in sorted(by_n.items()) if i not in order]
     checked = 0
-    for i in order[:6]:
+    for i in order:
+        print(f"uneven512 circuit {i}: n={circs[i]['n_qubits']} gates={len(circs[i]['gates'])}", flush=True)
         p = params[b.offsets[i]:b.offsets[i + 1]]
         E_ref, g_ref = O.grad_adjoint(circs[i], hams[i], p)
         tol = 1e-5 * _scale(hams[i])
         assert abs(E[i] - E_ref) <= tol
-        assert np.max(np.abs(g[b.offsets[i]:b.offsets[i + 1]] - g_ref)) <= 10 * tol
+        assert np.max(np.abs(g[b.offsets[i]:b.offsets[i + 1]] - g_ref)) <= tol
         checked += 1
     s_by_n = {}
     for i in range(len(circs)):
@@ -98,5 +107,5 @@ def test_uneven512_workload(Q):
         Ei, gi = Q.qsv_expectation_and_grad(s_by_n[n], circs[i], hams[i], p)
         tol = 1e-5 * _scale(hams[i])
         assert abs(E[i] - Ei) <= tol, (i, n)
-        assert np.max(np.abs(g[b.offsets[i]:b.offsets[i + 1]] - gi)) <= 10 * tol, (i, n)
-    assert checked == 6
+        assert np.max(np.abs(g[b.offsets[i]:b.offsets[i + 1]] - gi)) <= tol, (i, n)
+    assert checked == len(order) and len(by_n) == 13

@@ -43,9 +43,9 @@ def test_general_matches_oracle(Q, dtype, n, left, seed):
     E, gr, gl = Q.qsv_expectation_general(s_psi, cr, pr, s_phi, cl, pl if left else None, H)
     tol = TOL[dtype] * _scale(H)
     assert abs(E - E_ref) <= tol
-    assert np.max(np.abs(gr - gr_ref)) <= 10 * tol
+    assert np.max(np.abs(gr - gr_ref)) <= tol
     if left:
-        assert np.max(np.abs(gl - gl_ref)) <= 10 * tol
+        assert np.max(np.abs(gl - gl_ref)) <= tol
     assert np.array_equal(Q.qsv_state_get(s_psi), psi) and np.array_equal(Q.qsv_state_get(s_phi), phi)
 
 
@@ -73,4 +73,33 @@ def test_several_hamiltonians(Q, dtype):
         E_ref, g_ref = O.grad_adjoint(circ, H, params)
         tol = TOL[dtype] * _scale(H)
         assert abs(E[k] - E_ref) <= tol
-        assert np.max(np.abs(G[k] - g_ref)) <= 10 * tol
+        assert np.max(np.abs(G[k] - g_ref)) <= tol
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_general_u3_in_one_circuit_only(Q, dtype):
+    """U3 only in the right circuit (no left circuit, phi != psi): E and the complex
+    gradients depend on U3's global phase, which section 4.1's product
+    RZ(b) RX(-pi/2) RZ(a) RX(pi/2) RZ(c) fixes; the oracle builds U3 from that product."""
+    n = 5
+    rng = np.random.default_rng(9)
+    gates = []
+    for q in range(n):
+        gates.append(W.gate("U3", (q,), params=(W.param_angle(0), W.param_angle(1, 0.5), W.param_angle(2, -1.0, 0.3))))
+        gates.append(W.gate("X", ((q + 1) % n,), ctrls=(q,)))
+    cr = W.circuit(n, gates)
+    H = W.random_pauli_sum(n, 8, rng)
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    psi = W.random_state(n, rng).astype(npdt)
+    phi = W.random_state(n, rng).astype(npdt)
+    pr = rng.uniform(-2, 2, 3)
+    E_ref, gr_ref, _ = O.grad_general(cr, pr, psi.astype(complex), None, None, phi.astype(complex), H)
+    s_psi, s_phi = Q.qsv_state_create(n, dtype), Q.qsv_state_create(n, dtype)
+    Q.qsv_state_set(s_psi, psi)
+    Q.qsv_state_set(s_phi, phi)
+    E, gr, _ = Q.qsv_expectation_general(s_psi, cr, pr, s_phi, None, None, H)
+    tol = TOL[dtype] * _scale(H)
+    assert abs(E - E_ref) <= tol
+    assert np.max(np.abs(gr - gr_ref)) <= tol
+    # the standard-matrix U3 (section 4.1's product times e^{i(b+c)/2}) gives another E
+    assert abs(E_ref) > 1e-3
