@@ -218,6 +218,8 @@ void upload_plans(qsv_state* s, const UploadReq* reqs, int n_req, Uploaded* out)
 
 hipError_t launch_pass(const qsv_state* s, const DevPass& dp, PassArgs A, int batch, bool adj) {
   A.lr0 = dp.lr0;
+  A.lay0_reg = dp.lay0_reg;
+  A.lay0_thr = dp.lay0_thr;
   A.relayout = dp.rb ? dp.relayout : 0;
   A.win_lo = dp.win_lo;
   A.win_n = dp.rb ? dp.win_n : 0;

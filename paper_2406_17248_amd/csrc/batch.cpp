@@ -251,6 +251,8 @@ void build(qsv_batch* b) {
         A.n_qubits = b->circ[i].n;
         A.m = dp.m;
         A.lr0 = dp.lr0;
+        A.lay0_reg = dp.lay0_reg;
+        A.lay0_thr = dp.lay0_thr;
         A.win_lo = dp.win_lo;
         A.win_n = dp.win_n;
         A.pass_pslots = adjoint ? dp.pslot_count : 0;

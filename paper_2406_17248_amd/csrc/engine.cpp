@@ -630,6 +630,18 @@ std::vector<Pass> plan_rounds(const std::vector<Prim>& prims, const std::vector<
   return rounds;
 }
 
+RbLayout canonical_layout(uint32_t lr, int m, int r) {
+  RbLayout L;
+  L.r = r;
+  L.nt = m - r;
+  int i = 0, t = 0;
+  for (int bit = 0; bit < m; ++bit) {
+    if (lr >> bit & 1) L.reg[i++] = bit;
+    else L.thr[t++] = bit;
+  }
+  return L;
+}
+
 namespace {
 
 struct PassEmitter {
@@ -640,7 +652,8 @@ struct PassEmitter {
   uint64_t T;
   int loc[64];
   std::vector<int32_t> op_param;  // gradient parameter of each op of the pass (-1 none)
-  int32_t cur_lr = 0;             // register-blocked passes: current local register mask
+  bool rb = false;                // register-blocked pass
+  RbLayout lay;                   // register-blocked passes: the current register layout
 
   int alloc(int count) {
     const int off = plan.ctab_size;
@@ -659,16 +672,18 @@ struct PassEmitter {
   // Split a diagonal entry's local condition into its thread-index part and the set of
   // register slots that satisfy its register part, for the current register layout.
   void slot_masks(DiagEntry& d) const {
-    const uint32_t lr = (uint32_t)cur_lr;
+    if (!rb) {
+      d.tmask = d.lcmask;
+      d.kmask = 1;
+      return;
+    }
+    const uint32_t lr = lay.regmask();
     d.tmask = d.lcmask & ~lr;
     const uint32_t rm = d.lcmask & lr;
-    int pos[32], np = 0;
-    for (int bit = 0; bit < 32; ++bit)
-      if (lr >> bit & 1) pos[np++] = bit;
     d.kmask = 0;
-    for (int k = 0; k < (1 << np); ++k) {
+    for (int k = 0; k < (1 << lay.r); ++k) {
       uint32_t bits = 0;
-      for (int i = 0; i < np; ++i) bits |= (uint32_t)((k >> i) & 1) << pos[i];
+      for (int i = 0; i < lay.r; ++i) bits |= (uint32_t)((k >> i) & 1) << lay.reg[i];
       if ((bits & rm) == rm) d.kmask |= 1u << k;
     }
   }
@@ -676,13 +691,13 @@ struct PassEmitter {
   // sorted) its register class for the current register layout.
   ZZEdge edge_in_layout(int u, int v) const {
     ZZEdge ed{u, v, loc[u], loc[v], 0, 0, 0};
-    const uint32_t lr = (uint32_t)cur_lr;
     for (int q : {u, v}) {
       const int l = loc[q];
+      const int slot = (rb && l >= 0) ? lay.slot_of(l) : -1;
       if (l < 0) {
         ed.omask |= 1ull << q;
-      } else if (lr >> l & 1) {
-        ed.pad ^= 1u << __builtin_popcount(lr & ((1u << l) - 1));  // register index of bit l
+      } else if (slot >= 0) {
+        ed.pad ^= 1u << slot;
       } else {
         ed.tmask |= 1u << l;
       }
@@ -693,15 +708,35 @@ struct PassEmitter {
     plan.ops.push_back(op);
     op_param.push_back(param);
   }
-  void remap(int32_t lr) {
+  // Move to layout L through LDS.
+  void remap(const RbLayout& L) {
     TileOp op{};
     op.type = OP_REMAP;
-    op.a = lr;
-    for (int bit = 0, sh = 0; bit < 32; ++bit)
-      if (lr >> bit & 1) { op.b |= bit << sh; sh += 8; }
+    op.a = (int32_t)L.regmask();
+    op.b = (int32_t)L.regpack();
+    op.omask = L.thrpack();
     op.gen = -1;
     op.pslot = -1;
     push(op, -1);
+    lay = L;
+  }
+  // Transpositions (slot bit, lane bit) applied in order by cross-lane moves, one per op.
+  void xswap(const std::vector<std::pair<int, int>>& sw) {
+    for (const auto& ts : sw) {
+      TileOp op{};
+      op.type = OP_XSWAP;
+      op.count = 1;
+      const int i = ts.first, t = ts.second;
+      if (i < 0 || i >= lay.r || !lay.swappable(t)) fail(QSV_EINVAL, "internal: bad transposition");
+      std::swap(lay.reg[i], lay.thr[t]);
+      op.mat = (int32_t)(i | t << 4);
+      op.a = (int32_t)lay.regmask();
+      op.b = (int32_t)lay.regpack();
+      op.omask = lay.thrpack();
+      op.gen = -1;
+      op.pslot = -1;
+      push(op, -1);
+    }
   }
   // Diagonal primitives are buffered and emitted as late as possible: a dense primitive
   // commutes with every buffered diagonal one that does not touch its non-diagonal
@@ -793,14 +828,14 @@ struct PassEmitter {
             const int u = plan.prims[seq[r]].q0, v = plan.prims[seq[r]].q1;
             run.push_back(edge_in_layout(u, v));
           }
-          if (cur_lr != 0) {
+          if (rb) {
             // register-blocked: edges grouped by class, class sizes packed in a and b
             std::stable_sort(run.begin(), run.end(),
                              [](const ZZEdge& x, const ZZEdge& y) { return x.pad < y.pad; });
             // class masks with at most two bits in increasing order; the count of the
             // i-th is byte i of (a, b, lmask)
             std::vector<uint32_t> classes;
-            for (uint32_t c = 0; c < (1u << __builtin_popcount((uint32_t)cur_lr)); ++c)
+            for (uint32_t c = 0; c < (1u << lay.r); ++c)
               if (__builtin_popcount(c) <= 2) classes.push_back(c);
             uint32_t words[3] = {0, 0, 0};
             for (size_t i = 0; i < classes.size(); ++i) {
@@ -981,27 +1016,123 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
       const int r = reg_bits;
       const std::vector<Pass> rounds = plan_rounds(plan.prims, ps.prims, ps.tile_mask, r);
       const int32_t top = ((1 << r) - 1) << (ps.m - r);  // load/store layout
-      int32_t cur = -1;
-      for (size_t ri = 0; ri < rounds.size(); ++ri) {
+      const int R = (int)rounds.size();
+      // local register bits each round needs (0: the round has no one-qubit dense gate)
+      std::vector<uint32_t> need(R, 0);
+      for (int ri = 0; ri < R; ++ri) {
         bool has_dense = false;
         for (int32_t i : rounds[ri].prims) has_dense |= plan.prims[i].type == P_DENSE1;
-        const int32_t lr = round_layout(em, rounds[ri].tile_mask, ps.m, r);
-        if (cur < 0) {
-          // first round: load straight into its layout when the coalescing bits stay thread bits
-          cur = (has_dense && (lr & low_mask) == 0) ? lr : top;
-          dp.lr0 = em.cur_lr = cur;
+        if (has_dense) need[ri] = em.local_mask(rounds[ri].tile_mask);
+      }
+      auto next_use = [&](int bit, int from) {
+        for (int k = from; k < R; ++k)
+          if (need[k] >> bit & 1) return k;
+        return R + ps.m - bit;  // never again: the higher local bits first
+      };
+      em.rb = true;
+      bool started = false;
+      for (int ri = 0; ri < R; ++ri) {
+        if (!started) {
+          // first round: load straight into its layout when the coalescing bits stay thread
+          // bits in their places
+          const int32_t lr = need[ri] ? round_layout(em, rounds[ri].tile_mask, ps.m, r) : top;
+          em.lay = canonical_layout((uint32_t)((lr & low_mask) == 0 ? lr : top), ps.m, r);
+          dp.lr0 = (int32_t)em.lay.regmask();
+          dp.lay0_reg = em.lay.regpack();
+          dp.lay0_thr = em.lay.thrpack();
+          started = true;
         }
-        if (has_dense && lr != cur) {
-          em.remap(lr);
-          em.cur_lr = cur = lr;
+        if (need[ri] & ~em.lay.regmask()) {
+          const uint32_t miss = need[ri] & ~em.lay.regmask();
+          bool on_lanes = true;
+          for (int bit = 0; bit < ps.m; ++bit)
+            if (miss >> bit & 1) {
+              on_lanes &= em.lay.swappable(em.lay.thread_pos_of(bit));
+            }
+          if (on_lanes) {
+            // trade each missing bit for the register bit needed latest, by cross-lane moves
+            std::vector<std::pair<int, int>> sw;
+            RbLayout L = em.lay;
+            for (int bit = 0; bit < ps.m; ++bit) {
+              if (!(miss >> bit & 1)) continue;
+              int best = -1, best_use = -1;
+              for (int i = 0; i < r; ++i) {
+                if (need[ri] >> L.reg[i] & 1) continue;
+                const int u = next_use(L.reg[i], ri + 1);
+                if (u > best_use) { best_use = u; best = i; }
+              }
+              const int t = L.thread_pos_of(bit);
+              sw.push_back({best, t});
+              std::swap(L.reg[best], L.thr[t]);
+            }
+            em.xswap(sw);
+          } else {
+            // through LDS: the round's bits and those needed soonest in registers; the bits
+            // needed latest on the wave bits and the two needed soonest after the registers on
+            // lane bits 4 and 5 (where a later round can swap them in without LDS), never a
+            // coalescing bit; the rest on the other lanes in ascending order
+            RbLayout L;
+            L.r = r;
+            L.nt = ps.m - r;
+            std::vector<int> cand;
+            for (int bit = 0; bit < ps.m; ++bit)
+              if (!(need[ri] >> bit & 1)) cand.push_back(bit);
+            std::stable_sort(cand.begin(), cand.end(),
+                             [&](int x, int y) { return next_use(x, ri + 1) < next_use(y, ri + 1); });
+            uint32_t regs = need[ri];
+            for (size_t k = 0; k < cand.size() && popc(regs) < r; ++k) regs |= 1u << cand[k];
+            std::vector<int> rest;  // non-register, non-coalescing bits, soonest needed first
+            for (int bit : cand)
+              if (!(regs >> bit & 1) && bit >= low_local) rest.push_back(bit);
+            const int nl = L.lanes(), nw = L.nt - nl;
+            std::vector<int> pos(ps.m, -1);        // thread position of each non-register bit
+            std::vector<char> taken(L.nt, 0);
+            uint32_t placed = regs;
+            for (int k = 0; k < nw && k < (int)rest.size(); ++k) {  // wave bits: latest needed
+              const int bit = rest[rest.size() - 1 - k];
+              pos[bit] = nl + k;
+              taken[nl + k] = 1;
+              placed |= 1u << bit;
+            }
+            for (int h = 4; h <= 5 && h < nl; ++h) {  // lane bits 4, 5: soonest needed
+              for (int bit : rest) {
+                if (placed >> bit & 1) continue;
+                pos[bit] = h;
+                taken[h] = 1;
+                placed |= 1u << bit;
+                break;
+              }
+            }
+            for (int bit = 0, t = 0; bit < ps.m; ++bit) {  // the rest ascending
+              if (placed >> bit & 1) continue;
+              while (taken[t]) ++t;
+              pos[bit] = t;
+              taken[t] = 1;
+            }
+            int i = 0;
+            for (int bit = 0; bit < ps.m; ++bit) {
+              if (regs >> bit & 1) L.reg[i++] = bit;
+              else L.thr[pos[bit]] = bit;
+            }
+            em.remap(L);
+          }
         }
         int reg_index[32];
-        for (int bit = 0, ri2 = 0; bit < 32; ++bit) reg_index[bit] = (cur >> bit & 1) ? ri2++ : -1;
+        for (int bit = 0; bit < 32; ++bit) reg_index[bit] = -1;
+        for (int i = 0; i < r; ++i) reg_index[em.lay.reg[i]] = i;
         em.emit(rounds[ri].prims, reg_index);
       }
-      if (cur < 0) dp.lr0 = em.cur_lr = cur = top;
+      if (!started) {
+        em.lay = canonical_layout((uint32_t)top, ps.m, r);
+        dp.lr0 = top;
+        dp.lay0_reg = em.lay.regpack();
+        dp.lay0_thr = em.lay.thrpack();
+      }
       em.flush();
-      if (cur & low_mask) em.remap(top);
+      // stores: the coalescing local bits back on their own lanes
+      bool fixed = true;
+      for (int t = 0; t < low_local; ++t) fixed &= em.lay.thr[t] == t;
+      if (!fixed) em.remap(canonical_layout((uint32_t)top, ps.m, r));
     }
     // gradient slots: consecutive ops of one parameter share an accumulator
     if (adjoint) {

@@ -76,12 +76,57 @@ struct Fill {
   int32_t offset;     // ctab offset (complex entries)
 };
 
+// Register-blocked layout of a pass's tile: slot bit i of a thread's register block holds
+// local bit reg[i]; thread-index bit t holds local bit thr[t] (t < 6: a lane bit of the
+// wave, so amplitudes on it can trade places with a slot by cross-lane moves; higher t:
+// the wave within the workgroup, reachable only through LDS).
+struct RbLayout {
+  int32_t r = 0, nt = 0;
+  int32_t reg[4] = {0, 0, 0, 0};
+  int32_t thr[16] = {};
+  uint32_t regmask() const {
+    uint32_t m = 0;
+    for (int i = 0; i < r; ++i) m |= 1u << reg[i];
+    return m;
+  }
+  uint32_t regpack() const {
+    uint32_t p = 0;
+    for (int i = 0; i < r; ++i) p |= (uint32_t)reg[i] << (8 * i);
+    return p;
+  }
+  uint64_t thrpack() const {
+    uint64_t p = 0;
+    for (int t = 0; t < nt; ++t) p |= (uint64_t)thr[t] << (4 * t);
+    return p;
+  }
+  int slot_of(int bit) const {
+    for (int i = 0; i < r; ++i)
+      if (reg[i] == bit) return i;
+    return -1;
+  }
+  int thread_pos_of(int bit) const {
+    for (int t = 0; t < nt; ++t)
+      if (thr[t] == bit) return t;
+    return -1;
+  }
+  int lanes() const { return nt < 6 ? nt : 6; }
+  // thread bits a cross-lane transposition can use: lane bits 4 and 5 (the row and
+  // half-wave swaps); the others cost more VALU work than an LDS remap, which runs beside
+  // other waves' arithmetic
+  bool swappable(int t) const { return (t == 4 || t == 5) && t < nt; }
+};
+// Register bits = the set bits of lr (ascending), thread bits = the other local bits
+// (ascending).
+RbLayout canonical_layout(uint32_t lr, int m, int r);
+
 struct DevPass {
   uint64_t tile_mask;
   int32_t  m;
   int32_t  maxm;       // LDS capacity instantiation
   int32_t  rb;         // register-blocked kernel: its register bits (3 or 4); 0: LDS sweep
   int32_t  lr0;        // register-blocked: local register mask at load time
+  uint32_t lay0_reg;   // register-blocked: load layout (RbLayout::regpack / thrpack)
+  uint64_t lay0_thr;
   int32_t  op_first, op_count;
   int32_t  pslot_first, pslot_count;
   int32_t  win_lo, win_n;  // register-blocked: ctab window of the pass's per-lane lookups

@@ -410,6 +410,31 @@ __device__ __forceinline__ int swz(int j) {
   return j ^ (f & ((1 << S) - 1));
 }
 
+// dst <- src in the lanes set in the wave-uniform lane mask, written in place (a select
+// whose result the compiler could put in a new register would make it carry the register
+// block in two register sets).
+__device__ __forceinline__ void sel_in32(uint32_t& d, uint32_t src, uint64_t lanes) {
+  asm("v_cndmask_b32_e64 %0, %0, %1, %2" : "+v"(d) : "v"(src), "s"(lanes));
+}
+__device__ __forceinline__ void sel_in(float2& d, float2 s, uint64_t lanes) {
+  uint32_t x = __float_as_uint(d.x), y = __float_as_uint(d.y);
+  sel_in32(x, __float_as_uint(s.x), lanes);
+  sel_in32(y, __float_as_uint(s.y), lanes);
+  d.x = __uint_as_float(x);
+  d.y = __uint_as_float(y);
+}
+__device__ __forceinline__ void sel_in(double2& d, double2 s, uint64_t lanes) {
+  const uint64_t a = (uint64_t)__double_as_longlong(d.x), b = (uint64_t)__double_as_longlong(d.y);
+  const uint64_t e = (uint64_t)__double_as_longlong(s.x), f = (uint64_t)__double_as_longlong(s.y);
+  uint32_t w[4] = {(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
+  sel_in32(w[0], (uint32_t)e, lanes);
+  sel_in32(w[1], (uint32_t)(e >> 32), lanes);
+  sel_in32(w[2], (uint32_t)f, lanes);
+  sel_in32(w[3], (uint32_t)(f >> 32), lanes);
+  d.x = __longlong_as_double((long long)((uint64_t)w[1] << 32 | w[0]));
+  d.y = __longlong_as_double((long long)((uint64_t)w[3] << 32 | w[2]));
+}
+
 template <typename C> __device__ __forceinline__ C csel(bool c, C a, C b) {
   C r;
   r.x = c ? a.x : b.x;
@@ -417,11 +442,91 @@ template <typename C> __device__ __forceinline__ C csel(bool c, C a, C b) {
   return r;
 }
 
+// Cross-lane transposition of a register slot bit and lane bit L (4 or 5) of the wave.  X
+// and Y are the two slots that differ in the slot bit.  Afterwards X holds the amplitudes
+// whose old lane bit L was 0 and Y those whose old lane bit L was 1, each at the lane whose
+// bit L equals their old slot bit:
+//   X' = c ? Y(lane ^ 2^L) : X,   Y' = c ? Y : X(lane ^ 2^L)   (c = the lane's bit L),
+// which is what gfx950's row swap (bit 4: odd 16-lane rows of the first operand with even
+// rows of the second) and half-wave swap (bit 5) do, in place, one 32-bit word each.
+template <int L>
+__device__ __forceinline__ void xlane32(uint32_t& x, uint32_t& y) {
+  static_assert(L == 4 || L == 5, "cross-lane transpositions use lane bits 4 and 5");
+  if constexpr (L == 5) {
+    const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+    x = r[0];
+    y = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+    x = r[0];
+    y = r[1];
+  }
+}
+template <int L>
+__device__ __forceinline__ void xlane(float2& X, float2& Y) {
+  uint32_t x0 = __float_as_uint(X.x), x1 = __float_as_uint(X.y), y0 = __float_as_uint(Y.x), y1 = __float_as_uint(Y.y);
+  xlane32<L>(x0, y0);
+  xlane32<L>(x1, y1);
+  X.x = __uint_as_float(x0); X.y = __uint_as_float(x1);
+  Y.x = __uint_as_float(y0); Y.y = __uint_as_float(y1);
+}
+template <int L>
+__device__ __forceinline__ void xlane(double2& X, double2& Y) {
+  const uint64_t a = (uint64_t)__double_as_longlong(X.x), b = (uint64_t)__double_as_longlong(X.y);
+  const uint64_t e = (uint64_t)__double_as_longlong(Y.x), f = (uint64_t)__double_as_longlong(Y.y);
+  uint32_t x[4] = {(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
+  uint32_t y[4] = {(uint32_t)e, (uint32_t)(e >> 32), (uint32_t)f, (uint32_t)(f >> 32)};
+#pragma unroll
+  for (int d = 0; d < 4; ++d) xlane32<L>(x[d], y[d]);
+  X.x = __longlong_as_double((long long)((uint64_t)x[1] << 32 | x[0]));
+  X.y = __longlong_as_double((long long)((uint64_t)x[3] << 32 | x[2]));
+  Y.x = __longlong_as_double((long long)((uint64_t)y[1] << 32 | y[0]));
+  Y.y = __longlong_as_double((long long)((uint64_t)y[3] << 32 | y[2]));
+}
+template <int I, int L, int NR, typename C>
+__device__ __forceinline__ void xswap1(C* v) {
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    if (k & (1 << I)) continue;
+    xlane<L>(v[k], v[k | (1 << I)]);
+  }
+}
+// code = slot bit | lane bit << 4 (lane bit 4 or 5)
+template <int RB, typename C>
+__device__ __forceinline__ void xswap_dispatch(int code, C* v) {
+  constexpr int NR = 1 << RB;
+  switch (code) {
+    case 0 | 4 << 4: xswap1<0, 4, NR>(v); break;
+    case 0 | 5 << 4: xswap1<0, 5, NR>(v); break;
+    case 1 | 4 << 4: xswap1<1, 4, NR>(v); break;
+    case 1 | 5 << 4: xswap1<1, 5, NR>(v); break;
+    case 2 | 4 << 4: xswap1<2, 4, NR>(v); break;
+    case 2 | 5 << 4: xswap1<2, 5, NR>(v); break;
+    default:
+      if constexpr (RB > 3) {
+        if (code == (3 | 4 << 4)) xswap1<(RB > 3 ? 3 : 0), 4, NR>(v);
+        else if (code == (3 | 5 << 4)) xswap1<(RB > 3 ? 3 : 0), 5, NR>(v);
+      }
+      break;
+  }
+}
+
+// The local bits of register slot k in a layout whose slot bit i is local bit
+// (reg >> 8i) & 255 (wave-uniform).
+template <int NR>
+__device__ __forceinline__ int spread_of(uint32_t reg, int k) {
+  int j = 0;
+#pragma unroll
+  for (int i = 0; (1 << i) < NR; ++i)
+    if ((k >> i) & 1) j |= 1 << (int)((reg >> (8 * i)) & 255);
+  return j;
+}
+
 // 2x2 gate on register bit I.  Gates without local controls (the common case, a
 // wave-uniform test) run straight-line; controlled ones compute every pair and keep the
 // old values by select where a control bit is 0, so no lane-divergent branch is formed.
 template <int I, int NR, bool ADJ, typename C>
-__device__ __forceinline__ void reg1(C* v, C* w, const int* jk, uint32_t lm, const C* U, bool grad,
+__device__ __forceinline__ void reg1(C* v, C* w, int jt, uint32_t reg, uint32_t lm, const C* U, bool grad,
                                      const C* G, double& acc) {
   if (lm == 0) {
 #pragma unroll
@@ -444,7 +549,7 @@ __device__ __forceinline__ void reg1(C* v, C* w, const int* jk, uint32_t lm, con
   for (int k = 0; k < NR; ++k) {
     if (k & (1 << I)) continue;
     const int k1 = k | (1 << I);
-    const bool ok = ((uint32_t)jk[k] & lm) == lm;
+    const bool ok = ((uint32_t)(jt | spread_of<NR>(reg, k)) & lm) == lm;
     C n0 = v[k], n1 = v[k1];
     if (ADJ) {
       C m0 = w[k], m1 = w[k1];
@@ -452,12 +557,14 @@ __device__ __forceinline__ void reg1(C* v, C* w, const int* jk, uint32_t lm, con
       if (grad) g = im_conj_mul(m0, cdot2(G[0], n0, G[1], n1)) + im_conj_mul(m1, cdot2(G[2], n0, G[3], n1));
       apply2(U[0], U[1], U[2], U[3], m0, m1, g);
       acc += ok ? g : 0.0;
-      w[k] = csel(ok, m0, w[k]);
-      w[k1] = csel(ok, m1, w[k1]);
+      const uint64_t okm = __builtin_amdgcn_ballot_w64(ok);
+      sel_in(w[k], m0, okm);
+      sel_in(w[k1], m1, okm);
     }
     apply2(U[0], U[1], U[2], U[3], n0, n1);
-    v[k] = csel(ok, n0, v[k]);
-    v[k1] = csel(ok, n1, v[k1]);
+    const uint64_t okv = __builtin_amdgcn_ballot_w64(ok);
+    sel_in(v[k], n0, okv);
+    sel_in(v[k1], n1, okv);
   }
 }
 
@@ -472,15 +579,15 @@ __device__ __forceinline__ void mat4(const C* M, const C* x, C* y) {
 }
 
 template <int RB, bool ADJ, typename C>
-__device__ __forceinline__ void reg1_dispatch(int i, C* v, C* w, const int* jk, uint32_t lm, const C* U, bool grad,
+__device__ __forceinline__ void reg1_dispatch(int i, C* v, C* w, int jt, uint32_t reg, uint32_t lm, const C* U, bool grad,
                                               const C* G, double& acc) {
   constexpr int NR = 1 << RB;
   switch (i) {
-    case 0: reg1<0, NR, ADJ>(v, w, jk, lm, U, grad, G, acc); break;
-    case 1: reg1<1, NR, ADJ>(v, w, jk, lm, U, grad, G, acc); break;
-    case 2: reg1<2, NR, ADJ>(v, w, jk, lm, U, grad, G, acc); break;
+    case 0: reg1<0, NR, ADJ>(v, w, jt, reg, lm, U, grad, G, acc); break;
+    case 1: reg1<1, NR, ADJ>(v, w, jt, reg, lm, U, grad, G, acc); break;
+    case 2: reg1<2, NR, ADJ>(v, w, jt, reg, lm, U, grad, G, acc); break;
     default:
-      if constexpr (RB > 3) reg1<(RB > 3 ? 3 : 0), NR, ADJ>(v, w, jk, lm, U, grad, G, acc);
+      if constexpr (RB > 3) reg1<(RB > 3 ? 3 : 0), NR, ADJ>(v, w, jt, reg, lm, U, grad, G, acc);
       break;
   }
 }
@@ -587,40 +694,29 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
   const C* src = A.src ? reinterpret_cast<const C*>(A.src) + (int64_t)b * A.src_bstride : psi;
   const C* T = reinterpret_cast<const C*>(A.ctab) + (int64_t)b * A.ctab_bstride;
 
-  // Local index of register slot k: the thread id with zeros inserted at the RB register
-  // bits (ascending), plus the bits of k spread over them.
-  int jk[NR];
-  auto layout = [&](int lr, int* jo) {
-    int pos[RB];
-    int rest = lr;
+  // Local index of register slot k in a layout: thread bit t of the thread id sits at local
+  // bit (thr >> 4t) & 15, slot bit i of k at local bit (reg >> 8i) & 255.  A thread keeps
+  // only its own part jt (slot 0); the slot parts are wave-uniform.
+  const int nthr = m - RB;  // thread bits in use
+  auto layout = [&](uint64_t thr) {
+    // an opaque copy of the thread id, so the per-bit terms are not hoisted out of the op
+    // loop and kept live in registers for the whole pass
+    int tv = tid;
+    asm volatile("" : "+v"(tv));
+    int j = 0;
 #pragma unroll
-    for (int i = 0; i < RB; ++i) {
-      pos[i] = __builtin_ctz(rest);
-      rest &= rest - 1;
-    }
-    int jt = tid;
-#pragma unroll
-    for (int i = 0; i < RB; ++i) jt = insert_zero(jt, pos[i]);
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      int j = jt;
-#pragma unroll
-      for (int i = 0; i < RB; ++i) j |= ((k >> i) & 1) << pos[i];
-      jo[k] = j;
-    }
+    for (int t = 0; t < MAXM - RB; ++t)
+      if (t < nthr) j |= ((tv >> t) & 1) << (int)((thr >> (4 * t)) & 15);
+    return j;
   };
   // LDS byte address of register slot k.  swz is linear over GF(2) and slot k's local index is
   // the thread part (slot 0) with the bits of k spread over the register bits, so the address
   // is a per-thread term, swz(thread part), XOR a wave-uniform term, swz(spread of k): moving
   // a register block through LDS costs one XOR per slot.
-  auto slot_offsets = [&](int lr, int* off) {
+  auto slot_offsets = [&](uint32_t reg, int* off) {
     int u[RB];
-    int rest = lr;
 #pragma unroll
-    for (int i = 0; i < RB; ++i) {
-      u[i] = swz<S>(1 << __builtin_ctz(rest)) * (int)sizeof(C);
-      rest &= rest - 1;
-    }
+    for (int i = 0; i < RB; ++i) u[i] = swz<S>(1 << (int)((reg >> (8 * i)) & 255)) * (int)sizeof(C);
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       int o = 0;
@@ -651,15 +747,24 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
   for (int i = tid; i < win_n; i += NT) win[i] = T[win_lo + i];
   __syncthreads();
   auto tab = [&](int off) -> C { return win_n ? win[off - win_lo] : ldc(T + off); };
+
+  int jt = layout(A.lay0_thr);                         // the thread's part of its local indices
+  uint32_t reg_cur = A.lay0_reg;                       // register bits of the current layout
+  int sw_cur = swz<S>(jt) * (int)sizeof(C);            // per-thread term of its LDS addresses
   auto globals = [&](uint64_t tile_base, uint64_t* xo) {
 #pragma unroll
-    for (int k = 0; k < NR; ++k) xo[k] = tile_base | dep_lo[jk[k] & 127] | dep_hi[jk[k] >> 7];
+    for (int k = 0; k < NR; ++k) {
+      const int j = jt | spread_of<NR>(reg_cur, k);
+      xo[k] = tile_base | dep_lo[j & 127] | dep_hi[j >> 7];
+    }
   };
-  layout(A.lr0, jk);
-  int lr_cur = A.lr0;                                  // register bits of the current layout
-  int sw_cur = swz<S>(jk[0]) * (int)sizeof(C);         // per-thread term of its LDS addresses
 
   C v[NR], w[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    v[k] = C{0, 0};
+    if (ADJ) w[k] = C{0, 0};
+  }
   if (active) {
     uint64_t xk[NR];
     globals(A.relayout ? run_base(kRunsLoad) : base, xk);
@@ -689,7 +794,7 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
     const int ob = ld(&O->b);
     if (on && active && ((type == OP_DIAG && !ob) || (type == OP_DENSE1 && ob))) {
       uint32_t touched;
-      const uint32_t sm = sign_slots(A.diag + ld(&O->first), ld(&O->count), base, (uint32_t)jk[0], touched);
+      const uint32_t sm = sign_slots(A.diag + ld(&O->first), ld(&O->count), base, (uint32_t)jt, touched);
       // slots no entry can reach are skipped (a wave-uniform test): an entry on a register
       // bit reaches half of them
 #pragma unroll
@@ -700,39 +805,47 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
         if (ADJ) flip_sign(w[k], f);
       }
     }
-    if (type == OP_REMAP) {
-      const int lr = ld(&O->a);
-      int jn[NR], uo[NR], un[NR];
-      layout(lr, jn);
-      slot_offsets(lr_cur, uo);
-      slot_offsets(lr, un);
-      const int sw_new = swz<S>(jn[0]) * (int)sizeof(C);
-      if (active) {
-#pragma unroll
-        for (int k = 0; k < NR; ++k) lds_at(sw_cur ^ uo[k]) = v[k];
-      }
-      __syncthreads();
-      if (active) {
-#pragma unroll
-        for (int k = 0; k < NR; ++k) v[k] = lds_at(sw_new ^ un[k]);
-      }
-      if (ADJ) {
-        __syncthreads();
+    if (type == OP_REMAP || type == OP_XSWAP) {
+      // the new layout: register slot bits, thread bits, the thread's part of its indices
+      const uint32_t lr = (uint32_t)ld(&O->b);
+      const int jn = layout(ld(&O->omask));
+      const int sw_new = swz<S>(jn) * (int)sizeof(C);
+      if (type == OP_XSWAP) {
+        // one transposition per op, by cross-lane moves; every lane takes part (partners
+        // of active lanes are active)
+        const int code = ld(&O->mat) & 255;
+        xswap_dispatch<RB>(code, v);
+        if (ADJ) xswap_dispatch<RB>(code, w);
+      } else {
+        int uo[NR], un[NR];
+        slot_offsets(reg_cur, uo);
+        slot_offsets(lr, un);
         if (active) {
 #pragma unroll
-          for (int k = 0; k < NR; ++k) lds_at(sw_cur ^ uo[k]) = w[k];
+          for (int k = 0; k < NR; ++k) lds_at(sw_cur ^ uo[k]) = v[k];
         }
         __syncthreads();
         if (active) {
 #pragma unroll
-          for (int k = 0; k < NR; ++k) w[k] = lds_at(sw_new ^ un[k]);
+          for (int k = 0; k < NR; ++k) v[k] = lds_at(sw_new ^ un[k]);
         }
-      }
+        if (ADJ) {
+          __syncthreads();
+          if (active) {
 #pragma unroll
-      for (int k = 0; k < NR; ++k) jk[k] = jn[k];
-      lr_cur = lr;
+            for (int k = 0; k < NR; ++k) lds_at(sw_cur ^ uo[k]) = w[k];
+          }
+          __syncthreads();
+          if (active) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) w[k] = lds_at(sw_new ^ un[k]);
+          }
+        }
+        __syncthreads();
+      }
+      jt = jn;
+      reg_cur = lr;
       sw_cur = sw_new;
-      __syncthreads();
     } else if (on && active && type == OP_DENSE1) {
       const int mat = ld(&O->mat), gen = ld(&O->gen);
       C U[4], G[4];
@@ -743,7 +856,7 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
 #pragma unroll
         for (int r = 0; r < 4; ++r) G[r] = ldc(T + gen + r);
       }
-      reg1_dispatch<RB, ADJ>(ld(&O->a), v, w, jk, lmask, U, grad, G, acc);
+      reg1_dispatch<RB, ADJ>(ld(&O->a), v, w, jt, reg_cur, lmask, U, grad, G, acc);
     } else if (on && type == OP_DENSE2) {
       // two-qubit dense gate on local bits a, b, applied to the tile staged in LDS (no
       // gradient: parameterized two-qubit rotations are lowered to RZZ with basis changes)
@@ -751,7 +864,7 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
       const int lo = a < bb ? a : bb, hi = a < bb ? bb : a;
       const uint32_t lm = lmask;
       int uo[NR];
-      slot_offsets(lr_cur, uo);
+      slot_offsets(reg_cur, uo);
       auto apply_staged = [&](C (&reg)[NR]) {
         if (active) {
 #pragma unroll
@@ -797,15 +910,16 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
         const uint32_t lcm = ld(&d->lcmask);
         if (ld(&d->kind) == DIAG_SIGN) {
           const uint32_t tm = ld(&d->tmask);
-          if (((uint32_t)jk[0] & tm) == tm) sm ^= ld(&d->kmask);
+          if (((uint32_t)jt & tm) == tm) sm ^= ld(&d->kmask);
         } else {
           const int l0 = ld(&d->l0), l1 = ld(&d->l1), q0 = ld(&d->q0), q1 = ld(&d->q1);
           const int mat = ld(&d->mat);
           const int dg = ADJ ? ld(&d->gen) : -1;
 #pragma unroll
           for (int k = 0; k < NR; ++k) {
-            if (((uint32_t)jk[k] & lcm) != lcm) continue;
-            const int idx = gbit(jk[k], l0, q0) | (q1 >= 0 ? gbit(jk[k], l1, q1) << 1 : 0);
+            const int j = jt | spread_of<NR>(reg_cur, k);
+            if (((uint32_t)j & lcm) != lcm) continue;
+            const int idx = gbit(j, l0, q0) | (q1 >= 0 ? gbit(j, l1, q1) << 1 : 0);
             ph[k] = cmul(ph[k], tab(mat + idx));
             if (ADJ && dg >= 0) gw[k] += (double)tab(dg + idx).x;
           }
@@ -834,7 +948,6 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
       const int first = ld(&O->first), mat = ld(&O->mat), gen = ld(&O->gen);
       const uint32_t cw[3] = {(uint32_t)ld(&O->a), (uint32_t)ld(&O->b), lm_raw};
       const ZZEdge* ed = A.edges + first;
-      const uint32_t jt = (uint32_t)jk[0];
       constexpr int NCLS = zz_classes<RB>();
       int sum_a = 0, dcls[NCLS];
       int e = 0;

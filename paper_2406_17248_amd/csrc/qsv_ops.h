@@ -19,9 +19,13 @@ enum OpType : int32_t {
                   // x_u != x_v.  In register-blocked passes the edges are sorted by class
                   // (ZZEdge::tmask etc.): class i (the i-th register-bit mask with at most
                   // two bits) has byte i of (a, b, lmask) edges
-  OP_REMAP = 4,   // register-blocked passes: move amplitudes through LDS so that the
-                  // local bits in mask `a` become the register bits; `b` packs their
-                  // positions in ascending order, 8 bits each
+  OP_REMAP = 4,   // register-blocked passes: move amplitudes through LDS into a new
+                  // layout: register (slot) bit i holds local bit (b >> 8i) & 255, thread
+                  // bit t holds local bit (omask >> 4t) & 15; `a` is the register mask
+  OP_XSWAP = 5,   // register-blocked passes: one transposition, `mat` = slot bit (low 2
+                  // bits) | lane bit (4 or 5) << 4, exchanging the local bit on a register
+                  // slot bit with the one on lane bit 4 or 5 of the wave by cross-lane moves
+                  // (no LDS); the layout after it is given as for OP_REMAP (count = 1)
 };
 // In register-blocked passes each thread holds 2^RB amplitudes; DENSE1 then names a
 // register-bit index (a in [0, RB)) instead of a local bit, and the other ops are
@@ -122,6 +126,8 @@ struct PassArgs {
   int32_t      m;             // tile qubits = popcount(tile_mask)
   int32_t      n_pslots;
   int32_t      lr0;           // register-blocked passes: local register mask at load time
+  uint32_t     lay0_reg;      // register-blocked passes: load layout, packed as OP_REMAP's b
+  uint64_t     lay0_thr;      //   and omask
   int32_t      win_n;         // register-blocked passes: ctab entries [win_lo, win_lo + win_n)
                               // copied to LDS for per-lane table lookups (0: read ctab)
   int64_t      n_tiles;       // tiles of this state (column length of partials)

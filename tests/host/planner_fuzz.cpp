@@ -6,8 +6,12 @@
 // relayout) and bound; Pauli sums are validated and grouped; invalid circuits must be
 // rejected with QSV_EINVAL / QSV_ERANGE.  The structural facts checked on every plan:
 // every primitive is executed exactly once, each op's table offsets lie inside the bound
-// table, each pass's deposit entries and ops lie inside the plan's arrays.
+// table, each pass's deposit entries and ops lie inside the plan's arrays, and every
+// register layout of a register-blocked pass (load layout, after each LDS remap or
+// cross-lane transposition) is a bijection of the tile's local bits whose transpositions
+// name valid slot and lane bits and lead to the layout the op states.
 // Exit status 0 when every check holds.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <random>
@@ -78,8 +82,47 @@ static int check_plan(const Plan& p, const qsv_circuit& c, const std::vector<dou
       if (dp.rb && (dp.dep_first < 0 || dp.dep_first + kDepEntries > (int)p.deps.size())) return 2;
       if (dp.m < 1 || dp.m > c.n_qubits || __builtin_popcountll(dp.tile_mask) != dp.m) return 3;
     }
+    // register layouts of register-blocked passes: every layout is a bijection of the tile's
+    // local bits onto slot and thread bits; cross-lane transpositions name a slot bit and a
+    // lane bit of a full wave's lanes and lead exactly to the layout the op states; gates
+    // name register slots of the current layout
+    for (const DevPass& dp : p.passes) {
+      if (!dp.rb) continue;
+      const int r = dp.rb, nt = dp.m - r, lanes = nt < 6 ? nt : 6;
+      int reg[4], thr[16];
+      auto unpack = [&](uint32_t rp, uint64_t tp) {
+        uint32_t seen_bits = 0;
+        for (int i = 0; i < r; ++i) { reg[i] = (int)((rp >> (8 * i)) & 255); seen_bits |= 1u << reg[i]; }
+        for (int t = 0; t < nt; ++t) { thr[t] = (int)((tp >> (4 * t)) & 15); seen_bits |= 1u << thr[t]; }
+        return seen_bits == (1u << dp.m) - 1;
+      };
+      if (!unpack(dp.lay0_reg, dp.lay0_thr)) return 9;
+      for (int i = 0; i < dp.op_count; ++i) {
+        const TileOp& op = p.ops[dp.op_first + i];
+        if (op.type == OP_XSWAP) {
+          if (op.count != 1) return 10;
+          for (int s2 = 0; s2 < op.count; ++s2) {
+            const int code = (int)(((uint32_t)op.mat >> (8 * s2)) & 255u), sl = code & 3, ln = code >> 4;
+            if (sl >= r || ln >= lanes || (code & 12)) return 10;
+            std::swap(reg[sl], thr[ln]);
+          }
+          int reg2[4], thr2[16];
+          std::copy(reg, reg + 4, reg2);
+          std::copy(thr, thr + 16, thr2);
+          if (!unpack((uint32_t)op.b, op.omask)) return 11;
+          if (!std::equal(reg, reg + r, reg2) || !std::equal(thr, thr + nt, thr2)) return 11;
+        } else if (op.type == OP_REMAP) {
+          if (!unpack((uint32_t)op.b, op.omask)) return 12;
+          uint32_t rm = 0;
+          for (int k = 0; k < r; ++k) rm |= 1u << reg[k];
+          if ((uint32_t)op.a != rm) return 12;
+        } else if (op.type == OP_DENSE1 && (op.a < 0 || op.a >= r)) {
+          return 13;
+        }
+      }
+    }
     for (const TileOp& op : p.ops) {
-      if (op.mat >= p.ctab_size || op.gen >= p.ctab_size) return 4;
+      if (op.type != OP_XSWAP && (op.mat >= p.ctab_size || op.gen >= p.ctab_size)) return 4;
       if ((op.type == OP_DIAG && op.first + op.count > (int)p.diag.size()) ||
           (op.type == OP_ZZ && op.first + op.count > (int)p.edges.size()))
         return 5;
