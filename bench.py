@@ -14,7 +14,8 @@ gate) is above the vector ridge point and the dominant kernel's roofline is the 
 ALU: `roofline` gives its algorithmic flop rate from per-launch HIP event timings taken
 inside the timed steps on the library's stream.  Extra fields: gates/s, the same step in
 the other precision, adjoint-vs-parameter-shift gradient throughput on the 24-qubit QAOA
-batch, and the CPU oracle timed on a bounded sample.
+batch (with the adjoint pass's own roofline), the 10-qubit ansatz latency, and the CPU
+oracle timed on a bounded sample.
 """
 
 import argparse
@@ -86,10 +87,18 @@ def cpu_baseline_sample(n, depth, seconds):
             break
     dt = time.perf_counter() - t0
     assert np.isfinite(psi[0])
-    return {"value": bytes_ / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+    # the 10-qubit hardware-efficient ansatz: one energy-and-gradient evaluation by the oracle
+    circ10, H10, p10 = W.hea10_workload()
+    t1 = time.perf_counter()
+    reps = 0
+    while reps < 3 or time.perf_counter() - t1 < 1.0:
+        O.grad_adjoint(circ10, H10, p10)
+        reps += 1
+    hea10_s = (time.perf_counter() - t1) / reps
+    return {"value": bytes_ / dt / 1e9, "unit": "GB/s", "cores": 1, "host_cores": os.cpu_count(), "kind": "oracle",
             "sample": f"first {done} gate(s) of the {n}-qubit depth-{depth} brick circuit, complex128, "
                       f"numpy single thread, {dt:.1f} s",
-            "gates_per_s": done / dt}
+            "gates_per_s": done / dt, "hea10_grad_eval_s": hea10_s}
 
 
 def run_cpu_baseline(n, depth, seconds):
@@ -106,31 +115,110 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def qaoa_leg(Q, dtype, ps_sets):
-    """Adjoint batch gradient (64 sets) vs GPU parameter shift (ps_sets sets)."""
+def qaoa_flops(circ, n, adjoint):
+    """Algorithmic flop of one evaluation of the QAOA circuit per amplitude-pass, summed over
+    gates: a dense 2x2 gate is 14 flop per amplitude (two complex multiplies and a complex
+    add per output); a ZZ cost layer is one fused diagonal phase, 6 flop per amplitude (one
+    complex multiply; the edge parities are integer work).  The adjoint sweep applies U^dag to
+    both psi and lambda (twice the forward cost) and adds, per parameterized gate, 4 flop per
+    amplitude for its term Im<lambda|G|psi>.  Returns (forward, adjoint) flop per parameter set."""
+    N = float(2 ** n)
+    fwd = adj = 0.0
+    layer_open = False
+    for g in circ["gates"]:
+        if g["kind"] == "RZZ":
+            if not layer_open:  # one fused diagonal op per cost layer
+                fwd += 6 * N
+                adj += 2 * 6 * N
+                layer_open = True
+            adj += 4 * N
+        else:
+            layer_open = False
+            fwd += 14 * N
+            if g["kind"] != "H":  # the leading Hadamards act on the start state: never undone
+                adj += 2 * 14 * N + (4 * N if g["params"] else 0)
+    return fwd, adj
+
+
+def qaoa_leg(Q, dtype, ps_sets, with_copy=False):
+    """Adjoint batch gradient (64 sets) vs GPU parameter shift (ps_sets sets), with per-launch
+    HIP event timings of the adjoint evaluation (on the library's stream) for its roofline."""
     import numpy as np
 
     import workloads as W
     circ, H, params, _ = W.qaoa_workload()
+    n = circ["n_qubits"]
     c, h = Q.Circuit(circ), Q.PauliSum(H)
-    s = Q.qsv_state_create(24, dtype)
+    s = Q.qsv_state_create(n, dtype)
     Q.qsv_expectation_and_grad_batch(s, c, h, params[:2])  # warm plans and workspaces
+    Q.qsv_expectation_and_grad_batch(s, c, h, params)
+    Q.qsv_state_set_option(s, Q.OPT_PROFILE, 1)
+    for k in range(5):
+        Q.qsv_profile_read(s, k)
     t0 = time.perf_counter()
     E, G = Q.qsv_expectation_and_grad_batch(s, c, h, params)
     t_adj = time.perf_counter() - t0
+    prof = {k: Q.qsv_profile_read(s, k) for k in range(5)}
+    Q.qsv_state_set_option(s, Q.OPT_PROFILE, 0)
     log(f"qaoa adjoint batch of {params.shape[0]}: {t_adj:.3f} s")
-    t0 = time.perf_counter()
-    Eps, Gps = Q.qsv_param_shift_grad_batch(s, c, h, params[:ps_sets])
-    t_ps = time.perf_counter() - t0
-    log(f"qaoa parameter shift, {ps_sets} set(s): {t_ps:.3f} s")
     adj_rate = params.shape[0] / t_adj
-    ps_rate = ps_sets / t_ps
-    scale = sum(abs(cf) for cf, _ in H)
-    agree = float(np.max(np.abs(G[:ps_sets] - Gps)) / scale)
+    ps_rate = agree = None
+    if ps_sets > 0:
+        t0 = time.perf_counter()
+        Eps, Gps = Q.qsv_param_shift_grad_batch(s, c, h, params[:ps_sets])
+        t_ps = time.perf_counter() - t0
+        log(f"qaoa parameter shift, {ps_sets} set(s): {t_ps:.3f} s")
+        ps_rate = ps_sets / t_ps
+        scale = sum(abs(cf) for cf, _ in H)
+        agree = float(np.max(np.abs(G[:ps_sets] - Gps)) / scale)
+    if with_copy:
+        # plain copy kernel of known size (reads and writes 2^28 amplitudes once), for the
+        # calibration of hardware byte counters
+        a, d = Q.qsv_state_create(28, dtype), Q.qsv_state_create(28, dtype)
+        Q.qsv_state_copy(d, a)
+        Q.qsv_state_synchronize(d)
+        del a, d
     del s
+    B = params.shape[0]
+    f_fwd, f_adj = qaoa_flops(circ, n, True)
+    ms, launches, by = prof[Q.K_TILE_ADJOINT]
+    launches = max(launches, 1)
+    avg_s = ms / launches / 1e3
+    flop_launch = f_adj * B / launches
+    bytes_launch = by / launches
+    peak = VALU_PEAK_TFLOPS[dtype]
+    achieved = flop_launch / avg_s / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None, "kernel": "tile_pass_rb adjoint (psi and lambda, reverse sweep)",
+            "launches_per_eval": launches, "avg_launch_ms": avg_s * 1e3,
+            "algorithmic_flop_per_launch": flop_launch, "algorithmic_bytes_per_launch": bytes_launch,
+            "hbm_GBs": bytes_launch / avg_s / 1e9, "hbm_frac": bytes_launch / avg_s / 1e9 / HBM_PEAK_GBS,
+            "frac_of_nonpacked_peak": achieved / VALU_NONPACKED_TFLOPS}
+    kernel_ms = {name: prof[k][0] for name, k in
+                 (("tile_forward", Q.K_TILE_FORWARD), ("tile_adjoint", Q.K_TILE_ADJOINT), ("pauli", Q.K_PAULI),
+                  ("other", Q.K_OTHER))}
     return {"workload": "qaoa24_p8_batch64", "dtype": dtype, "adjoint_grad_evals_per_s": adj_rate,
-            "param_shift_grad_evals_per_s": ps_rate, "speedup": adj_rate / ps_rate,
-            "max_grad_diff_over_S": agree, "param_shift_sets": ps_sets}
+            "param_shift_grad_evals_per_s": ps_rate, "speedup": adj_rate / ps_rate if ps_rate else None,
+            "max_grad_diff_over_S": agree, "param_shift_sets": ps_sets,
+            "kernel_ms_per_batch": kernel_ms, "roofline": roof}
+
+
+def hea10_leg(Q, reps):
+    """10-qubit hardware-efficient ansatz (80 parameters), complex128: latency of one
+    expectation-and-gradient call through the C ABI (its 16 KiB state is latency-bound, no
+    roofline applies)."""
+    import workloads as W
+    circ, H, params = W.hea10_workload()
+    c, h = Q.Circuit(circ), Q.PauliSum(H)
+    s = Q.qsv_state_create(10, "c128")
+    for _ in range(3):
+        Q.qsv_expectation_and_grad(s, c, h, params)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        E, g = Q.qsv_expectation_and_grad(s, c, h, params)
+    dt = (time.perf_counter() - t0) / reps
+    return {"workload": "hea10_4layers_80params_zzchain", "dtype": "c128", "evals_per_s": 1.0 / dt,
+            "ms_per_eval": dt * 1e3, "reps": reps, "energy": E}
 
 
 def batch_leg(Q, reps=5):
@@ -256,6 +344,13 @@ def brick_leg(Q, torch, circ, H, n, dtype, steps, warmup, tile, with_copy):
     log(f"brick n={n} dtype={dtype}: {warmup} warmup step(s)")
     for _ in range(warmup):
         step()
+    # the same steps without per-launch events (their cost is two event records per ~20 ms launch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt_plain = (time.perf_counter() - t0) / steps
     Q.qsv_state_set_option(s, Q.OPT_PROFILE, 1)
     for k in range(5):
         Q.qsv_profile_read(s, k)
@@ -303,14 +398,11 @@ def brick_leg(Q, torch, circ, H, n, dtype, steps, warmup, tile, with_copy):
                  (("tile_forward", Q.K_TILE_FORWARD), ("pauli", Q.K_PAULI), ("gate_stream", Q.K_GATE_STREAM),
                   ("other", Q.K_OTHER))}
     value = total_bytes / dt / 1e9
-    # the same circuit gate by gate (one read + write of the state per dense gate, a quarter
-    # of it per CZ) at this step time: how far fusion moves past the unfused HBM floor
     state = float(2 ** n) * (8 if dtype == "c64" else 16)
-    unfused = n_dense * 2 * state + (n_gates - n_dense) * 2 * state / 4 + state
-    return {"value": value, "ms_per_step": dt * 1e3, "gates": n_gates, "gates_per_s": n_gates / dt,
+    return {"value": value, "ms_per_step": dt * 1e3, "ms_per_step_without_events": dt_plain * 1e3,
+            "gates": n_gates, "gates_per_s": n_gates / dt,
             "expectation": e, "kernel_ms_per_step": kernel_ms, "roofline": roofline,
-            "hbm_frac_of_peak": value / HBM_PEAK_GBS,
-            "unfused_equivalent_GBs": unfused / dt / 1e9, "state_bytes": int(state)}
+            "hbm_frac_of_peak": value / HBM_PEAK_GBS, "state_bytes": int(state)}
 
 
 def main():
@@ -326,9 +418,12 @@ def main():
     ap.add_argument("--no-qaoa", action="store_true")
     ap.add_argument("--no-other-dtype", action="store_true", help="skip the second precision")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-circuit batch leg")
+    ap.add_argument("--no-hea10", action="store_true", help="skip the 10-qubit ansatz latency leg")
+    ap.add_argument("--hea10-reps", type=int, default=200)
     ap.add_argument("--with-copy", action="store_true",
                     help="after the timed steps, run one plain state copy (counter calibration)")
     ap.add_argument("--ps-sets", type=int, default=1)
+    ap.add_argument("--qaoa-only", action="store_true", help="run only the QAOA adjoint leg in --dtype")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--warmstart", action="store_true",
@@ -357,6 +452,10 @@ def main():
     if args.warmstart:
         print(json.dumps(warmstart_leg(args.ws_train, args.ws_test, args.ws_epochs, args.ws_restarts)), flush=True)
         return 0
+    if args.qaoa_only:
+        # the adjoint leg alone in one precision (for profiler runs of its kernels)
+        print(json.dumps({"qaoa": [qaoa_leg(Q, args.dtype, args.ps_sets, args.with_copy)]}), flush=True)
+        return 0
     n, depth = args.n_qubits, args.depth
     circ, H = W.brick_workload(n, depth)
     main_leg = brick_leg(Q, torch, circ, H, n, args.dtype, args.steps, args.warmup, args.tile, args.with_copy)
@@ -369,15 +468,15 @@ def main():
                       "gates": main_leg["gates"],
                       "amplitude_type": "complex64" if args.dtype == "c64" else "complex128",
                       "state_bytes": main_leg["state_bytes"], "parallelism": "single-gpu"}}
-    for k in ("gates_per_s", "expectation", "hbm_frac_of_peak", "unfused_equivalent_GBs", "kernel_ms_per_step",
+    for k in ("gates_per_s", "expectation", "hbm_frac_of_peak", "ms_per_step_without_events", "kernel_ms_per_step",
               "roofline"):
         out[k] = main_leg[k]
     other = "c64" if args.dtype == "c128" else "c128"
     if not args.no_other_dtype:
         leg = brick_leg(Q, torch, circ, H, n, other, args.steps, args.warmup, args.tile, False)
         out["other_dtype"] = {"dtype": other, **{k: leg[k] for k in ("value", "ms_per_step", "gates_per_s",
-                                                                   "expectation", "unfused_equivalent_GBs",
-                                                                   "roofline")}}
+                                                                   "expectation", "ms_per_step_without_events",
+                                                                   "kernel_ms_per_step", "roofline")}}
     if not args.no_qaoa:
         out["qaoa"] = []
         for dt_ in ([args.dtype] if args.no_other_dtype else [args.dtype, other]):
@@ -385,6 +484,11 @@ def main():
                 out["qaoa"].append(qaoa_leg(Q, dt_, args.ps_sets))
             except Exception as ex:  # report, do not hide, a failure of the secondary leg
                 out["qaoa"].append({"dtype": dt_, "error": repr(ex)})
+    if not args.no_hea10:
+        try:
+            out["hea10"] = hea10_leg(Q, args.hea10_reps)
+        except Exception as ex:  # report, do not hide, a failure of the secondary leg
+            out["hea10"] = {"error": repr(ex)}
     if not args.no_batch:
         try:
             out["batch"] = batch_leg(Q)
@@ -393,6 +497,9 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, single thread)")
         out["cpu_baseline"] = run_cpu_baseline(n, depth, args.cpu_seconds)
+        if "hea10" in out and "evals_per_s" in out["hea10"] and "hea10_grad_eval_s" in out["cpu_baseline"]:
+            out["hea10"]["oracle_s_per_eval"] = out["cpu_baseline"]["hea10_grad_eval_s"]
+            out["hea10"]["speedup_vs_oracle"] = out["hea10"]["evals_per_s"] * out["cpu_baseline"]["hea10_grad_eval_s"]
     print(json.dumps(out), flush=True)
     return 0
 
