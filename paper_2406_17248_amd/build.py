@@ -16,6 +16,10 @@ HIPCC_FLAGS = [
     # branches: structurizing them makes old and new register blocks live at once, and the
     # pass then copies its whole register block after every op.
     "-mllvm", "-structurizecfg-skip-uniform-regions=true",
+    # Matrix-core operands and results in ordinary VGPRs: otherwise the fused-block op pulls
+    # the whole register block into accumulation registers, which every other op must then
+    # copy in and out.
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function",
 ]
 

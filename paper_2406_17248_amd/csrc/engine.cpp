@@ -265,6 +265,15 @@ PlanOptions state_plan_options(int32_t dtype, int32_t n, int32_t tile, int32_t a
   // complex64 forward passes keep 16 amplitudes per thread (registers still allow 4 waves
   // per SIMD): fewer REMAPs and half the per-op and per-tile work per amplitude
   if (!adjoint && dtype == QSV_C64) o.reg_bits = 4;
+  // complex64 forward passes fuse three-qubit rounds of one-qubit gates into matrix-core
+  // blocks, keeping a round's blocks when they average at least 3 gates: fp32 matrix
+  // cores run at twice the rate of the (unpacked) fp32 vector ALU, so a block of 16x16x4
+  // products costs about two register gates plus its layout moves (measured on the brick
+  // and QAOA circuits, 3 is the best threshold of 2 / 2.5 / 3 / 3.5).  Complex128 blocks
+  // would cost about four gates (fp64 matrix and vector rates are equal) and measured
+  // slower on the brick circuit.
+  o.blocks = !adjoint && dtype == QSV_C64;
+  o.block_min_gates = 3.0;
   return o;
 }
 
@@ -745,16 +754,57 @@ struct PassEmitter {
   std::vector<int32_t> pending;
   uint64_t pending_touched = 0;
 
+  // Fused blocks (block rounds of forward register-blocked passes): the round's one-qubit
+  // gates, and the diagonal primitives between them that act only on the block's qubits,
+  // are multiplied into one 8x8 matrix on (lane bit 4, lane bit 5, register slot bslot).
+  bool bmode = false;
+  uint64_t bq = 0;            // global qubits of the block
+  int32_t bqs[3] = {0, 0, 0}; // global qubit of block index bits 0..2
+  int32_t bslot = -1;
+  int32_t open = -1;          // the open block (index in plan.blocks), -1 if none
+  void close_block() {
+    if (open < 0) return;
+    TileOp op{};
+    op.type = OP_BLOCK;
+    op.a = bslot;
+    op.mat = alloc(128);
+    op.gen = -1;
+    op.pslot = -1;
+    plan.fills.push_back({F_BLOCK, open, 0, op.mat});
+    push(op, -1);
+    open = -1;
+  }
+  bool absorbs(const Prim& p) const {
+    if (p.type == P_DENSE1) return p.cmask == 0 && (bq >> p.q0 & 1);
+    if (p.type == P_SIGN || p.type == P_DIAG1 || p.type == P_DIAG2) return open >= 0 && (p.touched & ~bq) == 0;
+    return false;
+  }
+
   // Emit ops for primitives seq (in order).  reg_index: for register-blocked passes the
   // register index of each local bit (-1 if not a register bit), else nullptr.
   void emit(const std::vector<int32_t>& seq, const int* reg_index) {
     for (int32_t pi : seq) {
       const Prim& p = plan.prims[pi];
+      if (bmode && absorbs(p)) {
+        if (pending_touched & p.nondiag) {
+          // pending diagonal primitives act on the gate's qubit before it: the block so far
+          // goes first, then they, then a new block
+          close_block();
+          flush();
+        }
+        if (open < 0) {
+          plan.blocks.push_back({{bqs[0], bqs[1], bqs[2]}, {}});
+          open = (int32_t)plan.blocks.size() - 1;
+        }
+        plan.blocks[open].prims.push_back(pi);
+        continue;
+      }
       if (!(p.type == P_DENSE1 || p.type == P_DENSE2)) {
         pending.push_back(pi);
         pending_touched |= p.touched;
         continue;
       }
+      close_block();
       TileOp pre{};
       bool has_pre = false;
       if (pending_touched & p.nondiag) {
@@ -803,6 +853,7 @@ struct PassEmitter {
   }
 
   void flush() {
+    close_block();
     const std::vector<int32_t> seq = pending;
     pending.clear();
     pending_touched = 0;
@@ -921,6 +972,7 @@ int32_t round_layout(const PassEmitter& em, uint64_t round_mask, int m, int r) {
 Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
   Plan plan;
   plan.adjoint = adjoint;
+  plan.dtype = opt.dtype;
   plan.n_qubits = c->n_qubits;
   plan.prims = adjoint ? lower_adjoint(c) : lower_forward(c);
   const int n = c->n_qubits;
@@ -1014,20 +1066,87 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
       em.flush();
     } else {
       const int r = reg_bits;
-      const std::vector<Pass> rounds = plan_rounds(plan.prims, ps.prims, ps.tile_mask, r);
+      // fused-block passes plan rounds of three qubits (the block size) and run each round
+      // whose dense work is all uncontrolled one-qubit gates as blocks; other rounds stay
+      // register rounds
+      const bool use_blocks = opt.blocks && !adjoint && ps.m - r >= 6;
+      const std::vector<Pass> rounds = plan_rounds(plan.prims, ps.prims, ps.tile_mask, use_blocks ? 3 : r);
       const int32_t top = ((1 << r) - 1) << (ps.m - r);  // load/store layout
       const int R = (int)rounds.size();
-      // local register bits each round needs (0: the round has no one-qubit dense gate)
+      // local bits each round needs in registers (0: the round has no one-qubit dense gate)
       std::vector<uint32_t> need(R, 0);
+      std::vector<char> blockable(R, 0);
       for (int ri = 0; ri < R; ++ri) {
-        bool has_dense = false;
-        for (int32_t i : rounds[ri].prims) has_dense |= plan.prims[i].type == P_DENSE1;
+        bool has_dense = false, simple = true;
+        for (int32_t i : rounds[ri].prims) {
+          const Prim& pr = plan.prims[i];
+          has_dense |= pr.type == P_DENSE1;
+          simple &= pr.type != P_DENSE2 && !(pr.type == P_DENSE1 && pr.cmask != 0);
+        }
         if (has_dense) need[ri] = em.local_mask(rounds[ri].tile_mask);
+        blockable[ri] = use_blocks && has_dense && simple;
       }
       auto next_use = [&](int bit, int from) {
         for (int k = from; k < R; ++k)
           if (need[k] >> bit & 1) return k;
         return R + ps.m - bit;  // never again: the higher local bits first
+      };
+      // A layout reached through LDS: register bits `regs` (slot order ascending, or `slot2`
+      // first at slot `slot2_at`), the bits `l4` / `l5` (if >= 0) on lane bits 4 / 5, the bits
+      // needed latest on the wave bits, the two needed soonest after them on lane bits 4 and 5
+      // if still free, never a coalescing bit on a wave bit or lanes 4, 5; the rest ascending.
+      auto lds_layout = [&](uint32_t regs, int l4, int l5, int slot2, int from) {
+        RbLayout L;
+        L.r = r;
+        L.nt = ps.m - r;
+        std::vector<int> cand;
+        for (int bit = 0; bit < ps.m; ++bit)
+          if (!(regs >> bit & 1) && bit != l4 && bit != l5 && bit >= low_local) cand.push_back(bit);
+        std::stable_sort(cand.begin(), cand.end(),
+                         [&](int x, int y) { return next_use(x, from) < next_use(y, from); });
+        const int nl = L.lanes(), nw = L.nt - nl;
+        std::vector<int> pos(ps.m, -1);
+        std::vector<char> taken(L.nt, 0);
+        uint32_t placed = regs;
+        auto put = [&](int bit, int t) {
+          pos[bit] = t;
+          taken[t] = 1;
+          placed |= 1u << bit;
+        };
+        if (l4 >= 0) put(l4, 4);
+        if (l5 >= 0) put(l5, 5);
+        for (int k = 0; k < nw && k < (int)cand.size(); ++k) put(cand[cand.size() - 1 - k], nl + k);
+        for (int h = 4; h <= 5 && h < nl; ++h) {
+          if (taken[h]) continue;
+          for (int bit : cand)
+            if (!(placed >> bit & 1)) { put(bit, h); break; }
+        }
+        for (int bit = 0, t = 0; bit < ps.m; ++bit) {
+          if (placed >> bit & 1) continue;
+          while (taken[t]) ++t;
+          put(bit, t);
+        }
+        int i = 0;
+        for (int bit = 0; bit < ps.m; ++bit) {
+          if (regs >> bit & 1) L.reg[i++] = bit;
+          else L.thr[pos[bit]] = bit;
+        }
+        if (slot2 >= 0) {  // put slot2's bit on slot slot2_at = 0
+          const int at = L.slot_of(slot2);
+          std::swap(L.reg[0], L.reg[at]);
+        }
+        return L;
+      };
+      // register bits for a round: its own and those needed soonest
+      auto fill_regs = [&](uint32_t base_regs, int from, uint32_t exclude) {
+        std::vector<int> cand;
+        for (int bit = 0; bit < ps.m; ++bit)
+          if (!(base_regs >> bit & 1) && !(exclude >> bit & 1)) cand.push_back(bit);
+        std::stable_sort(cand.begin(), cand.end(),
+                         [&](int x, int y) { return next_use(x, from) < next_use(y, from); });
+        uint32_t regs = base_regs;
+        for (size_t k = 0; k < cand.size() && popc(regs) < r; ++k) regs |= 1u << cand[k];
+        return regs;
       };
       em.rb = true;
       bool started = false;
@@ -1035,12 +1154,108 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
         if (!started) {
           // first round: load straight into its layout when the coalescing bits stay thread
           // bits in their places
-          const int32_t lr = need[ri] ? round_layout(em, rounds[ri].tile_mask, ps.m, r) : top;
+          const int32_t lr =
+              (need[ri] && !blockable[ri]) ? round_layout(em, rounds[ri].tile_mask, ps.m, r) : top;
           em.lay = canonical_layout((uint32_t)((lr & low_mask) == 0 ? lr : top), ps.m, r);
           dp.lr0 = (int32_t)em.lay.regmask();
           dp.lay0_reg = em.lay.regpack();
           dp.lay0_thr = em.lay.thrpack();
           started = true;
+        }
+        // A block round is kept only when its blocks carry enough gates to beat the
+        // register path on the vector ALU; otherwise everything it emitted is undone and the
+        // round runs as a register round.
+        struct Saved {
+          size_t ops, diag, edges, fills, blocks, op_param;
+          int32_t ctab;
+          std::vector<int32_t> pending;
+          uint64_t pending_touched;
+          RbLayout lay;
+        };
+        const Saved sv{plan.ops.size(), plan.diag.size(), plan.edges.size(), plan.fills.size(),
+                       plan.blocks.size(), em.op_param.size(), plan.ctab_size, em.pending,
+                       em.pending_touched, em.lay};
+        if (blockable[ri]) {
+          // block round: two of its qubits on lane bits 4 and 5, the third on a slot bit
+          const uint32_t tb = need[ri];
+          bool reachable = true;
+          for (int bit = 0; bit < ps.m; ++bit)
+            if (tb >> bit & 1) {
+              const int t = em.lay.thread_pos_of(bit);
+              reachable &= em.lay.slot_of(bit) >= 0 || t == 4 || t == 5;
+            }
+          if (reachable) {
+            RbLayout L = em.lay;
+            std::vector<std::pair<int, int>> sw;
+            auto on_lane = [&](int bit) { return L.thr[4] == bit || L.thr[5] == bit; };
+            int n_lane = 0, n_t = popc(tb);
+            for (int bit = 0; bit < ps.m; ++bit) n_lane += (tb >> bit & 1) && on_lane(bit);
+            // a slot's target moves onto a lane bit 4 / 5 whose bit is not a target
+            while ((n_t == 3 && n_lane < 2) || (n_t == 2 && n_lane == 0)) {
+              int from_slot = -1;
+              for (int i = 0; i < r && from_slot < 0; ++i)
+                if (tb >> L.reg[i] & 1) from_slot = i;
+              int lane = -1, best = -1;
+              for (int h = 4; h <= 5; ++h) {
+                if (tb >> L.thr[h] & 1) continue;
+                const int u = next_use(L.thr[h], ri + 1);
+                if (u > best) { best = u; lane = h; }
+              }
+              sw.push_back({from_slot, lane});
+              std::swap(L.reg[from_slot], L.thr[lane]);
+              ++n_lane;
+            }
+            em.xswap(sw);
+          } else {
+            // through LDS: two targets on lanes 4 and 5, the third on slot 0
+            std::vector<int> tbits;
+            for (int bit = 0; bit < ps.m; ++bit)
+              if (tb >> bit & 1) tbits.push_back(bit);
+            const int l4 = tbits.size() > 0 ? tbits[0] : -1, l5 = tbits.size() > 1 ? tbits[1] : -1;
+            const int s2 = tbits.size() > 2 ? tbits[2] : -1;
+            uint32_t excl = 0;
+            if (l4 >= 0) excl |= 1u << l4;
+            if (l5 >= 0) excl |= 1u << l5;
+            const uint32_t regs = fill_regs(s2 >= 0 ? 1u << s2 : 0u, ri + 1, excl);
+            em.remap(lds_layout(regs, l4, l5, s2, ri + 1));
+          }
+          // the block: lane bits 4, 5 and the slot holding the round's third qubit (or slot 0)
+          int slot = 0;
+          for (int i = 0; i < r; ++i)
+            if (tb >> em.lay.reg[i] & 1) slot = i;
+          em.bslot = slot;
+          const int lb[3] = {em.lay.thr[4], em.lay.thr[5], em.lay.reg[slot]};
+          em.bq = 0;
+          for (int t = 0; t < 3; ++t) {
+            int gq = -1;
+            for (int q = 0; q < 64; ++q)
+              if (em.loc[q] == lb[t]) gq = q;
+            em.bqs[t] = gq;
+            em.bq |= 1ull << gq;
+          }
+          em.bmode = true;
+          int reg_index[32];
+          for (int bit = 0; bit < 32; ++bit) reg_index[bit] = -1;
+          for (int i = 0; i < r; ++i) reg_index[em.lay.reg[i]] = i;
+          em.emit(rounds[ri].prims, reg_index);
+          em.close_block();
+          em.bmode = false;
+          int n_blocks = 0, n_gates = 0;
+          for (size_t b = sv.blocks; b < plan.blocks.size(); ++b) {
+            ++n_blocks;
+            for (int32_t pi : plan.blocks[b].prims) n_gates += plan.prims[pi].type == P_DENSE1;
+          }
+          if (n_gates >= opt.block_min_gates * n_blocks) continue;
+          plan.ops.resize(sv.ops);
+          plan.diag.resize(sv.diag);
+          plan.edges.resize(sv.edges);
+          plan.fills.resize(sv.fills);
+          plan.blocks.resize(sv.blocks);
+          em.op_param.resize(sv.op_param);
+          plan.ctab_size = sv.ctab;
+          em.pending = sv.pending;
+          em.pending_touched = sv.pending_touched;
+          em.lay = sv.lay;
         }
         if (need[ri] & ~em.lay.regmask()) {
           const uint32_t miss = need[ri] & ~em.lay.regmask();
@@ -1067,54 +1282,8 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
             }
             em.xswap(sw);
           } else {
-            // through LDS: the round's bits and those needed soonest in registers; the bits
-            // needed latest on the wave bits and the two needed soonest after the registers on
-            // lane bits 4 and 5 (where a later round can swap them in without LDS), never a
-            // coalescing bit; the rest on the other lanes in ascending order
-            RbLayout L;
-            L.r = r;
-            L.nt = ps.m - r;
-            std::vector<int> cand;
-            for (int bit = 0; bit < ps.m; ++bit)
-              if (!(need[ri] >> bit & 1)) cand.push_back(bit);
-            std::stable_sort(cand.begin(), cand.end(),
-                             [&](int x, int y) { return next_use(x, ri + 1) < next_use(y, ri + 1); });
-            uint32_t regs = need[ri];
-            for (size_t k = 0; k < cand.size() && popc(regs) < r; ++k) regs |= 1u << cand[k];
-            std::vector<int> rest;  // non-register, non-coalescing bits, soonest needed first
-            for (int bit : cand)
-              if (!(regs >> bit & 1) && bit >= low_local) rest.push_back(bit);
-            const int nl = L.lanes(), nw = L.nt - nl;
-            std::vector<int> pos(ps.m, -1);        // thread position of each non-register bit
-            std::vector<char> taken(L.nt, 0);
-            uint32_t placed = regs;
-            for (int k = 0; k < nw && k < (int)rest.size(); ++k) {  // wave bits: latest needed
-              const int bit = rest[rest.size() - 1 - k];
-              pos[bit] = nl + k;
-              taken[nl + k] = 1;
-              placed |= 1u << bit;
-            }
-            for (int h = 4; h <= 5 && h < nl; ++h) {  // lane bits 4, 5: soonest needed
-              for (int bit : rest) {
-                if (placed >> bit & 1) continue;
-                pos[bit] = h;
-                taken[h] = 1;
-                placed |= 1u << bit;
-                break;
-              }
-            }
-            for (int bit = 0, t = 0; bit < ps.m; ++bit) {  // the rest ascending
-              if (placed >> bit & 1) continue;
-              while (taken[t]) ++t;
-              pos[bit] = t;
-              taken[t] = 1;
-            }
-            int i = 0;
-            for (int bit = 0; bit < ps.m; ++bit) {
-              if (regs >> bit & 1) L.reg[i++] = bit;
-              else L.thr[pos[bit]] = bit;
-            }
-            em.remap(L);
+            // through LDS: the round's bits and those needed soonest in registers
+            em.remap(lds_layout(fill_regs(need[ri], ri + 1, 0), -1, -1, -1, ri + 1));
           }
         }
         int reg_index[32];
@@ -1273,6 +1442,63 @@ void gate_angles(const qsv_gate& g, const double* params, double out[3]) {
   }
 }
 
+void block_operands(const cplx* M8, int dtype, double* out) {
+  double mr[16][16] = {};
+  auto row = [](int beta, int ri) { return (beta & 3) + 4 * ri + 8 * (beta >> 2); };
+  for (int bo = 0; bo < 8; ++bo)
+    for (int bi = 0; bi < 8; ++bi) {
+      const double a = M8[bo * 8 + bi].real(), b = M8[bo * 8 + bi].imag();
+      mr[row(bo, 0)][row(bi, 0)] = a;
+      mr[row(bo, 0)][row(bi, 1)] = -b;
+      mr[row(bo, 1)][row(bi, 0)] = b;
+      mr[row(bo, 1)][row(bi, 1)] = a;
+    }
+  for (int l = 0; l < 64; ++l)
+    for (int j = 0; j < 4; ++j) {
+      const int m = l % 16, col = 4 * j + l / 16;
+      const int src = dtype == QSV_C64 ? (m / 4) + 4 * (m % 4) : m;
+      out[4 * l + j] = mr[src][col];
+    }
+}
+
+// The 8x8 matrix of a fused block: its primitives multiplied in execution order.
+static void block_matrix(const Plan& p, const qsv_circuit* c, const std::vector<double>& ang, const BlockSpec& b,
+                         cplx* M) {
+  for (int i = 0; i < 64; ++i) M[i] = (i % 9 == 0) ? 1.0 : 0.0;
+  auto bit_of = [&](int q) {
+    for (int t = 0; t < 3; ++t)
+      if (b.q[t] == q) return t;
+    return -1;
+  };
+  for (int32_t pi : b.prims) {
+    const Prim& pr = p.prims[pi];
+    cplx num[16];
+    prim_numbers(pr, c, &ang[3 * pr.gate], num);
+    if (pr.type == P_DENSE1) {
+      const int t = bit_of(pr.q0);
+      for (int col = 0; col < 8; ++col)
+        for (int beta = 0; beta < 8; ++beta) {
+          if (beta >> t & 1) continue;
+          const int b1 = beta | 1 << t;
+          const cplx x = M[beta * 8 + col], y = M[b1 * 8 + col];
+          M[beta * 8 + col] = num[0] * x + num[1] * y;
+          M[b1 * 8 + col] = num[2] * x + num[3] * y;
+        }
+      continue;
+    }
+    for (int beta = 0; beta < 8; ++beta) {
+      bool ctrl = true;
+      for (uint64_t cm = pr.cmask; cm; cm &= cm - 1) ctrl &= (beta >> bit_of(__builtin_ctzll(cm)) & 1) != 0;
+      if (!ctrl) continue;
+      cplx f;
+      if (pr.type == P_SIGN) f = -1.0;
+      else if (pr.type == P_DIAG1) f = num[beta >> bit_of(pr.q0) & 1];
+      else f = num[(beta >> bit_of(pr.q0) & 1) | (beta >> bit_of(pr.q1) & 1) << 1];
+      for (int col = 0; col < 8; ++col) M[beta * 8 + col] *= f;
+    }
+  }
+}
+
 void bind_ctab(const Plan& p, const qsv_circuit* c, const double* params, const AngleOverride* ov, int n_ov,
                cplx* out) {
   std::vector<double> ang(3 * c->n_gates);
@@ -1299,6 +1525,14 @@ void bind_ctab(const Plan& p, const qsv_circuit* c, const double* params, const 
       case F_ZZ_GEN: {
         const Prim& pr = p.prims[f.prim];
         for (int cc = 0; cc <= f.count; ++cc) dst[cc] = cplx(pr.coeff * (double)(f.count - 2 * cc), 0.0);
+        break;
+      }
+      case F_BLOCK: {
+        cplx M[64];
+        block_matrix(p, c, ang, p.blocks[f.prim], M);
+        double r[256];
+        block_operands(M, p.dtype, r);
+        for (int e = 0; e < 128; ++e) dst[e] = cplx(r[2 * e], r[2 * e + 1]);
         break;
       }
       default:

@@ -68,6 +68,8 @@ enum FillKind : int32_t {
   F_PRIM_GEN,         // coeff * generator of the primitive: same sizes (diag: real weights)
   F_ZZ_PHASES,        // exp(-+ i theta/2 (E - 2c)), c = 0..E (sign by dagger)
   F_ZZ_GEN,           // coeff * (E - 2c) as real weights
+  F_BLOCK,            // the product of a fused block's primitives as matrix-core operands
+                      // (Fill::prim indexes Plan::blocks; 128 entries)
 };
 struct Fill {
   int32_t kind;
@@ -135,8 +137,16 @@ struct DevPass {
 };
 
 // A fully planned execution (forward or adjoint reverse sweep) of one circuit structure.
+// A fused block of primitives applied as one dense 8x8 matrix: q[b] is the global qubit of
+// block index bit b (b = 0, 1 on lane bits 4 and 5, b = 2 on a register slot bit).
+struct BlockSpec {
+  int32_t q[3];
+  std::vector<int32_t> prims;  // in execution order
+};
+
 struct Plan {
   bool adjoint = false;
+  int32_t dtype = 1;
   bool unfused = false;     // per-primitive streaming kernels
   int32_t n_qubits = 0;
   std::vector<Prim> prims;
@@ -151,6 +161,7 @@ struct Plan {
   std::vector<DiagEntry> diag;
   std::vector<ZZEdge> edges;
   std::vector<Fill> fills;
+  std::vector<BlockSpec> blocks;    // fused blocks (OP_BLOCK)
   int32_t ctab_size = 0;            // complex entries per batch item
   std::vector<int32_t> pslot_param; // adjoint: parameter of each gradient slot
   int32_t n_pslots = 0;
@@ -168,7 +179,19 @@ struct PlanOptions {
   int32_t rb_min = 9;         // smallest register-blocked tile (smaller ones idle threads)
   int32_t reg_bits = 3;       // register bits of register-blocked passes (3, or 4 forward)
   bool    relayout = false;   // forward register-blocked plans: relayout between passes
+  bool    blocks = false;     // forward register-blocked plans: fuse the one-qubit gates of
+                              // three-qubit rounds into 8x8 blocks on the matrix cores
+  double  block_min_gates = 3.0;  // ... keeping a round's blocks when they average this many
+                                  // one-qubit gates
 };
+
+// Block index bit b of an 8x8 fused block and the real 16x16 matrix-core operands: the real
+// row of (block index beta, real/imaginary part ri) is (beta & 3) + 4 ri + 8 (beta >> 2); lane
+// l's A operand for k-chunk j (j = 0..3) is row l % 16, column 4 j + l / 16 of the matrix
+// whose rows are permuted as the accumulator layout of the amplitude type requires
+// (complex64: accumulator row 4q + v holds real row q + 4v; complex128: row r holds row r).
+// out receives 256 reals, lane-major (lane l's four values at 4l).
+void block_operands(const cplx* M8, int dtype, double* out);
 
 // Default tile widths of forward and adjoint plans, measured on the 30-qubit brick circuit
 // (forward) and the 24-qubit QAOA batch (adjoint): wider tiles save passes but need more

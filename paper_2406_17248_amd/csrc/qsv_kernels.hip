@@ -592,6 +592,61 @@ __device__ __forceinline__ void reg1_dispatch(int i, C* v, C* w, int jt, uint32_
   }
 }
 
+// Fused 8x8 block on (lane bit 4, lane bit 5, slot bit I) with the matrix cores.  A lane
+// holds, for each pair of slots (k0, k1 = k0 | 2^I), the block components
+// (re k0, im k0, re k1, im k1): real rows q + 4i of the 16-row real vector, q = its lane
+// bits 4-5, i = 0..3; its lane bits 0-3 select one of 16 columns.  Four 16x16x4 products
+// (k-chunk i = component i) give the 16x16 result, whose accumulator layout the planner's
+// row order already matches, so every component returns to the register it came from.
+typedef float qsv_f4 __attribute__((ext_vector_type(4)));
+typedef double qsv_d4 __attribute__((ext_vector_type(4)));
+template <int I, int NR>
+__device__ __forceinline__ void block16(float2* v, const float* a) {
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    if (k & (1 << I)) continue;
+    const int k1 = k | (1 << I);
+    qsv_f4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], v[k].x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], v[k].y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], v[k1].x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], v[k1].y, acc, 0, 0, 0);
+    v[k].x = acc[0];
+    v[k].y = acc[1];
+    v[k1].x = acc[2];
+    v[k1].y = acc[3];
+  }
+}
+template <int I, int NR>
+__device__ __forceinline__ void block16(double2* v, const double* a) {
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    if (k & (1 << I)) continue;
+    const int k1 = k | (1 << I);
+    qsv_d4 acc = {0.0, 0.0, 0.0, 0.0};
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], v[k].x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], v[k].y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], v[k1].x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], v[k1].y, acc, 0, 0, 0);
+    v[k].x = acc[0];
+    v[k].y = acc[1];
+    v[k1].x = acc[2];
+    v[k1].y = acc[3];
+  }
+}
+template <int RB, typename C, typename R>
+__device__ __forceinline__ void block_dispatch(int slot, C* v, const R* a) {
+  constexpr int NR = 1 << RB;
+  switch (slot) {
+    case 0: block16<0, NR>(v, a); break;
+    case 1: block16<1, NR>(v, a); break;
+    case 2: block16<2, NR>(v, a); break;
+    default:
+      if constexpr (RB > 3) block16<(RB > 3 ? 3 : 0), NR>(v, a);
+      break;
+  }
+}
+
 __device__ __forceinline__ int insert_zero(int t, int p) { return ((t >> p) << (p + 1)) | (t & ((1 << p) - 1)); }
 
 // Dynamic LDS of the register-blocked passes, sized per launch: the ctab window, then
@@ -846,6 +901,13 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
       jt = jn;
       reg_cur = lr;
       sw_cur = sw_new;
+    } else if (!ADJ && active && type == OP_BLOCK) {
+      // the lane's four A operands: 4 consecutive reals at 4 * lane of the block's table
+      const R* ap = reinterpret_cast<const R*>(T + ld(&O->mat)) + 4 * (tid & 63);
+      R a[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[j] = ap[j];
+      block_dispatch<RB>(ld(&O->a), v, a);
     } else if (on && active && type == OP_DENSE1) {
       const int mat = ld(&O->mat), gen = ld(&O->gen);
       C U[4], G[4];

@@ -26,6 +26,11 @@ enum OpType : int32_t {
                   // bits) | lane bit (4 or 5) << 4, exchanging the local bit on a register
                   // slot bit with the one on lane bit 4 or 5 of the wave by cross-lane moves
                   // (no LDS); the layout after it is given as for OP_REMAP (count = 1)
+  OP_BLOCK = 6,   // register-blocked forward passes: a dense 8x8 complex matrix on the local
+                  // bits of lane bit 4 (block index bit 0), lane bit 5 (bit 1) and register
+                  // slot bit `a` (bit 2), applied with matrix-core instructions (16x16x4):
+                  // ctab[mat .. mat + 128) holds its real 16x16 form as each lane's four
+                  // A-operand values, lane-major (see block_operands)
 };
 // In register-blocked passes each thread holds 2^RB amplitudes; DENSE1 then names a
 // register-bit index (a in [0, RB)) instead of a local bit, and the other ops are

@@ -9,7 +9,9 @@
 // table, each pass's deposit entries and ops lie inside the plan's arrays, and every
 // register layout of a register-blocked pass (load layout, after each LDS remap or
 // cross-lane transposition) is a bijection of the tile's local bits whose transpositions
-// name valid slot and lane bits and lead to the layout the op states.
+// name valid slot and lane bits and lead to the layout the op states, and every fused block's
+// matrix-core operands decode to the real form of a complex matrix, unitary when its gates
+// are (every kind but the explicit matrices, which this fuzzer draws at random).
 // Exit status 0 when every check holds.
 #include <algorithm>
 #include <cmath>
@@ -74,6 +76,8 @@ static void random_circuit(Circ& k, int n, int n_gates, int n_params, std::mt199
   k.c = qsv_circuit{n, 0, k.gates.data(), k.gates.size(), k.mats.data(), k.mats.size()};
 }
 
+static int g_unitary_blocks = 0;  // fused blocks whose unitarity was checked
+
 static int check_plan(const Plan& p, const qsv_circuit& c, const std::vector<double>& params, int& checks) {
   std::vector<int> seen(p.prims.size(), 0);
   if (!p.unfused) {
@@ -118,6 +122,8 @@ static int check_plan(const Plan& p, const qsv_circuit& c, const std::vector<dou
           if ((uint32_t)op.a != rm) return 12;
         } else if (op.type == OP_DENSE1 && (op.a < 0 || op.a >= r)) {
           return 13;
+        } else if (op.type == OP_BLOCK && (op.a < 0 || op.a >= r || nt < 6 || op.mat + 128 > p.ctab_size)) {
+          return 14;
         }
       }
     }
@@ -137,6 +143,42 @@ static int check_plan(const Plan& p, const qsv_circuit& c, const std::vector<dou
   bind_ctab(p, &c, params.data(), nullptr, 0, tab.data());
   for (const cplx& v : tab)
     if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return 8;
+  // fused blocks: the matrix-core operands decode to a unitary 8x8 matrix (read back through
+  // the lane-major A-operand layout, the accumulator row order of the amplitude type and the
+  // real embedding of complex numbers, each written out here independently of the planner)
+  for (const Fill& f : p.fills) {
+    if (f.kind != F_BLOCK) continue;
+    const auto& bs = p.blocks[f.prim];
+    if (bs.q[0] == bs.q[1] || bs.q[0] == bs.q[2] || bs.q[1] == bs.q[2]) return 15;
+    bool unitary_gates = true;  // this fuzzer's explicit matrices are not unitary
+    for (int32_t pi : bs.prims) {
+      const int kind = c.gates[p.prims[pi].gate].kind;
+      unitary_gates &= kind != QSV_GATE_MAT1 && kind != QSV_GATE_MAT2;
+    }
+    double mp[16][16], mr[16][16];
+    for (int l = 0; l < 64; ++l)
+      for (int j = 0; j < 4; ++j) {
+        const cplx e = tab[f.offset + (4 * l + j) / 2];
+        mp[l % 16][4 * j + l / 16] = ((4 * l + j) % 2) ? e.imag() : e.real();
+      }
+    for (int m = 0; m < 16; ++m)
+      for (int k = 0; k < 16; ++k) mr[p.dtype == QSV_C64 ? (m / 4) + 4 * (m % 4) : m][k] = mp[m][k];
+    auto row = [](int beta, int ri) { return (beta & 3) + 4 * ri + 8 * (beta >> 2); };
+    cplx M[8][8];
+    for (int bo = 0; bo < 8; ++bo)
+      for (int bi = 0; bi < 8; ++bi) {
+        const double a = mr[row(bo, 0)][row(bi, 0)], b = mr[row(bo, 1)][row(bi, 0)];
+        if (mr[row(bo, 1)][row(bi, 1)] != a || mr[row(bo, 0)][row(bi, 1)] != -b) return 16;
+        M[bo][bi] = cplx(a, b);
+      }
+    g_unitary_blocks += unitary_gates;
+    for (int i = 0; i < 8 && unitary_gates; ++i)
+      for (int j = 0; j < 8; ++j) {
+        cplx d = 0.0;
+        for (int k = 0; k < 8; ++k) d += std::conj(M[k][i]) * M[k][j];
+        if (std::abs(d - (i == j ? 1.0 : 0.0)) > 1e-12) return 17;
+      }
+  }
   ++checks;
   return 0;
 }
@@ -226,5 +268,6 @@ int main() {
     return 2;
   }
   printf("plans checked: %d\n", checks);
-  return bad || checks < 1000;
+  printf("unitary fused blocks checked: %d\n", g_unitary_blocks);
+  return bad || checks < 1000 || g_unitary_blocks < 100;
 }
