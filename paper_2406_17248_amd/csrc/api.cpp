@@ -310,22 +310,67 @@ struct DevPauli {
   std::vector<PauliGroup> groups;
   std::vector<const uint64_t*> z;
   std::vector<const double*> cre, cim;
+  std::vector<const uint32_t*> pats;   // diagonal groups over >= 12 qubits, else null
+  std::vector<const int32_t*> rfirst;
+  std::vector<int32_t> n_pats;
 };
 
-// Bytes of the groups' term tables (z masks, coefficient real and imaginary parts, each
-// array `align`-byte aligned).
-size_t pauli_table_bytes(const std::vector<PauliGroup>& groups, size_t align = 256) {
+// A diagonal group's terms sorted by their pattern on the 12 low qubits, with the pattern
+// table of PauliGroupArgs::pats / rfirst (empty when the group does not qualify).
+void pattern_tables(PauliGroup& g, int n, std::vector<uint32_t>& pats, std::vector<int32_t>& rfirst) {
+  pats.clear();
+  rfirst.clear();
+  if (g.xmask != 0 || n < 12 || g.zmasks.empty()) return;
+  std::vector<size_t> ord(g.zmasks.size());
+  for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
+  std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+    return (g.zmasks[a] & 0xFFF) < (g.zmasks[b] & 0xFFF);
+  });
+  PauliGroup h = g;
+  for (size_t k = 0; k < ord.size(); ++k) {
+    h.zmasks[k] = g.zmasks[ord[k]];
+    h.cre[k] = g.cre[ord[k]];
+    h.cim[k] = g.cim[ord[k]];
+  }
+  for (size_t k = 0; k < h.zmasks.size(); ++k) {
+    const uint32_t pat = (uint32_t)(h.zmasks[k] & 0xFFF);
+    if (pats.empty() || (pats.back() & 0xFFF) != pat) pats.push_back(pat | (uint32_t)k << 12);
+  }
+  if (pats.size() > (size_t)kPauliMaxPatterns || h.zmasks.size() >= (1u << 20)) {
+    pats.clear();
+    return;
+  }
+  for (int r = 0, p = 0; r <= 16; ++r) {
+    while (p < (int)pats.size() && (int)((pats[p] & 0xFFF) >> 8) < r) ++p;
+    rfirst.push_back(p);
+  }
+  g = h;
+}
+
+// Bytes of the groups' term tables (z masks, coefficient real and imaginary parts, and for
+// qualifying diagonal groups the pattern tables, each array `align`-byte aligned).  Sorts
+// the terms of diagonal groups by pattern (pattern_tables).
+size_t pauli_table_bytes(std::vector<PauliGroup>& groups, int n, size_t align = 256) {
   size_t total = 0;
-  for (auto& g : groups) total += align_up(g.zmasks.size() * 8, align) * 3;
+  std::vector<uint32_t> pats;
+  std::vector<int32_t> rfirst;
+  for (auto& g : groups) {
+    total += align_up(g.zmasks.size() * 8, align) * 3;
+    pattern_tables(g, n, pats, rfirst);
+    if (!pats.empty()) total += align_up(pats.size() * 4, align) + align_up(rfirst.size() * 4, align);
+  }
   return total;
 }
 
 // Pack the tables into host bytes `host`; the returned pointers are where they sit once
-// the bytes are copied to device address `dev`.
-DevPauli pack_pauli(std::vector<PauliGroup> groups, char* host, char* dev, size_t align = 256) {
+// the bytes are copied to device address `dev`.  The groups must have passed through
+// pauli_table_bytes (diagonal groups sorted).
+DevPauli pack_pauli(std::vector<PauliGroup> groups, int n, char* host, char* dev, size_t align = 256) {
   DevPauli dp;
   dp.groups = std::move(groups);
   size_t off = 0;
+  std::vector<uint32_t> pats;
+  std::vector<int32_t> rfirst;
   for (auto& g : dp.groups) {
     const size_t sz = g.zmasks.size() * 8, al = align_up(sz, align);
     std::memcpy(host + off, g.zmasks.data(), sz);
@@ -335,17 +380,31 @@ DevPauli pack_pauli(std::vector<PauliGroup> groups, char* host, char* dev, size_
     dp.cre.push_back(reinterpret_cast<const double*>(dev + off + al));
     dp.cim.push_back(reinterpret_cast<const double*>(dev + off + 2 * al));
     off += 3 * al;
+    pattern_tables(g, n, pats, rfirst);  // already sorted: this only rebuilds the tables
+    if (pats.empty()) {
+      dp.pats.push_back(nullptr);
+      dp.rfirst.push_back(nullptr);
+      dp.n_pats.push_back(0);
+      continue;
+    }
+    std::memcpy(host + off, pats.data(), pats.size() * 4);
+    dp.pats.push_back(reinterpret_cast<const uint32_t*>(dev + off));
+    off += align_up(pats.size() * 4, align);
+    std::memcpy(host + off, rfirst.data(), rfirst.size() * 4);
+    dp.rfirst.push_back(reinterpret_cast<const int32_t*>(dev + off));
+    off += align_up(rfirst.size() * 4, align);
+    dp.n_pats.push_back((int32_t)pats.size());
   }
   return dp;
 }
 
 DevPauli upload_pauli(qsv_state* s, const qsv_pauli_sum* h, DevBuf& buf) {
   std::vector<PauliGroup> groups = group_pauli_sum(h);
-  const size_t bytes = pauli_table_bytes(groups);
+  const size_t bytes = pauli_table_bytes(groups, s->n);
   const size_t total = bytes ? bytes : 256;
   char* st = static_cast<char*>(stage_acquire(s, total));
   buf.reserve(total);
-  DevPauli dp = pack_pauli(std::move(groups), st, static_cast<char*>(buf.p));
+  DevPauli dp = pack_pauli(std::move(groups), s->n, st, static_cast<char*>(buf.p));
   hip_check(hipMemcpyAsync(buf.p, st, total, hipMemcpyHostToDevice, s->stream), "upload pauli");
   stage_release_after_queue(s);
   return dp;
@@ -389,6 +448,9 @@ void run_pauli(qsv_state* s, const DevPauli& dp, const void* psi, void* lam, int
     A.col = 2 * (g - g0);
     A.ncols = nc;
     A.real_coeffs = std::all_of(dp.groups[g].cim.begin(), dp.groups[g].cim.end(), [](double c) { return c == 0.0; });
+    A.pats = dp.pats[g];
+    A.rfirst = dp.rfirst[g];
+    A.n_pats = dp.n_pats[g];
     // read psi; write lambda (and read it when accumulating)
     const double sb = (double)batch * (double)s->namps() * (double)s->amp_bytes();
     const double bytes = sb * (1.0 + (lam ? 1.0 : 0.0) + (lam && g > 0 ? 1.0 : 0.0));
@@ -758,13 +820,13 @@ int qsv_expectation_noalloc(qsv_state* s, const qsv_pauli_sum* h, double* out_re
     double re = 0, im = 0;
     if (G > 0) {
       // scratch layout: term tables | reduced columns | partials of kNoallocChunk groups
-      const size_t tab = pauli_table_bytes(groups, 8);
+      const size_t tab = pauli_table_bytes(groups, s->n, 8);
       const size_t out_off = align_up(tab, 256);
       const size_t part_off = align_up(out_off + (size_t)2 * G * sizeof(double), 256);
       const size_t part_bytes = (size_t)2 * kNoallocChunk * pauli_blocks(s->n) * sizeof(double);
       if (part_off + part_bytes > kNoallocScratchBytes) fail(QSV_ERANGE, "Pauli sum too large for the fixed scratch");
       std::vector<char> host(tab);
-      DevPauli dp = pack_pauli(std::move(groups), host.data(), scr, 8);
+      DevPauli dp = pack_pauli(std::move(groups), s->n, host.data(), scr, 8);
       hip_check(hipMemcpyAsync(scr, host.data(), tab, hipMemcpyHostToDevice, s->stream), "upload pauli");
       double* d_out = reinterpret_cast<double*>(scr + out_off);
       run_pauli(s, dp, s->psi, nullptr, 0, 1, d_out, reinterpret_cast<double*>(scr + part_off), kNoallocChunk, true);

@@ -265,15 +265,15 @@ PlanOptions state_plan_options(int32_t dtype, int32_t n, int32_t tile, int32_t a
   // complex64 forward passes keep 16 amplitudes per thread (registers still allow 4 waves
   // per SIMD): fewer REMAPs and half the per-op and per-tile work per amplitude
   if (!adjoint && dtype == QSV_C64) o.reg_bits = 4;
-  // complex64 forward passes fuse three-qubit rounds of one-qubit gates into matrix-core
-  // blocks, keeping a round's blocks when they average at least 3 gates: fp32 matrix
-  // cores run at twice the rate of the (unpacked) fp32 vector ALU, so a block of 16x16x4
-  // products costs about two register gates plus its layout moves (measured on the brick
-  // and QAOA circuits, 3 is the best threshold of 2 / 2.5 / 3 / 3.5).  Complex128 blocks
-  // would cost about four gates (fp64 matrix and vector rates are equal) and measured
-  // slower on the brick circuit.
-  o.blocks = !adjoint && dtype == QSV_C64;
-  o.block_min_gates = 3.0;
+  // forward passes fuse three-qubit rounds of one-qubit gates into matrix-core blocks,
+  // keeping a round's blocks when they average enough gates.  complex64: fp32 matrix cores
+  // run at twice the rate of the (unpacked) fp32 vector ALU, so a block of 16x16x4 products
+  // costs about two register gates plus its layout moves; 3 is the best threshold of
+  // 2 / 2.5 / 3 / 3.5 on the brick and QAOA circuits.  complex128: fp64 matrix and vector
+  // rates are equal, so a block costs about four gates, but the matrix cores run beside the
+  // vector ALU's other work; 4.5 is the best of 3.5 / 4.5 / 5.5 / none (brick: -7 %).
+  o.blocks = !adjoint;
+  o.block_min_gates = dtype == QSV_C64 ? 3.0 : 4.5;
   return o;
 }
 

@@ -1215,7 +1215,85 @@ __global__ __launch_bounds__(256) void pauli_group(PauliGroupArgs A) {
   const uint64_t N = 1ull << A.n_qubits;
   const uint64_t stride = (uint64_t)gridDim.x * 256;
   double er = 0.0, ei = 0.0;
-  if (A.xmask == 0 && A.n_qubits >= 2) {
+  if (A.xmask == 0 && A.n_pats > 0) {
+    // Diagonal group, in chunks of 4096 consecutive amplitudes x = hi | i << 8 | t (t the
+    // thread, i = 0..15 its slot).  A term's sign splits into a per-chunk part on hi and a
+    // part on the 12 low bits, so per chunk the coefficient of each low pattern p is
+    // C_p = sum_k c_k (-1)^{popcount(hi & z_k)} over the terms with that pattern; a thread
+    // folds its own bits into E_r = sum over patterns with bits 8-11 equal to r of
+    // C_p (-1)^{popcount(t & p)}, and a 16-point Walsh-Hadamard transform gives
+    // f(x) = sum_r E_r (-1)^{popcount(i & r)} for its 16 slots.  Each term costs a few
+    // operations per chunk instead of per amplitude, which leaves the pass bound by HBM.
+    __shared__ double cpr[kPauliMaxPatterns], cpi[kPauliMaxPatterns];
+    const int P = A.n_pats;
+    const bool real_c = A.real_coeffs;
+    const int tid = threadIdx.x;
+    const uint64_t n_chunks = N >> 12;
+    for (uint64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
+      const uint64_t hi = ch << 12;
+      __syncthreads();  // the previous chunk's readers of cpr / cpi are done
+      for (int p = tid; p < P; p += 256) {
+        const int k0 = (int)(A.pats[p] >> 12);
+        const int k1 = p + 1 < P ? (int)(A.pats[p + 1] >> 12) : A.n_terms;
+        double sr = 0.0, si = 0.0;
+        for (int k = k0; k < k1; ++k) {
+          const bool neg = __popcll(hi & A.zmasks[k]) & 1;
+          sr += neg ? -A.cre[k] : A.cre[k];
+          if (!real_c) si += neg ? -A.cim[k] : A.cim[k];
+        }
+        cpr[p] = sr;
+        cpi[p] = si;
+      }
+      __syncthreads();
+      double fr[16], fi[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        double a = 0.0, b = 0.0;
+        const int p0 = ld(A.rfirst + r), p1 = ld(A.rfirst + r + 1);
+        for (int p = p0; p < p1; ++p) {
+          const uint32_t pat = ld(A.pats + p) & 0xFFu;
+          const bool neg = __popc((uint32_t)tid & pat) & 1;
+          a += neg ? -cpr[p] : cpr[p];
+          if (!real_c) b += neg ? -cpi[p] : cpi[p];
+        }
+        fr[r] = a;
+        fi[r] = b;
+      }
+      // Walsh-Hadamard transform over the 4 slot bits
+#pragma unroll
+      for (int h = 1; h < 16; h <<= 1) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          if (r & h) continue;
+          const double a = fr[r], b = fr[r | h];
+          fr[r] = a + b;
+          fr[r | h] = a - b;
+          if (!real_c) {
+            const double c2 = fi[r], d = fi[r | h];
+            fi[r] = c2 + d;
+            fi[r | h] = c2 - d;
+          }
+        }
+      }
+      C v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = psi[hi | (uint64_t)(i << 8) | (uint64_t)tid];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const double pi = (double)v[i].x * v[i].x + (double)v[i].y * v[i].y;
+        er += pi * fr[i];
+        ei += pi * fi[i];
+        if (lam) {
+          const uint64_t x = hi | (uint64_t)(i << 8) | (uint64_t)tid;
+          C o;
+          o.x = (R)(fr[i] * v[i].x - fi[i] * v[i].y);
+          o.y = (R)(fr[i] * v[i].y + fi[i] * v[i].x);
+          if (A.accumulate) { const C l = lam[x]; o.x += l.x; o.y += l.y; }
+          lam[x] = o;
+        }
+      }
+    }
+  } else if (A.xmask == 0 && A.n_qubits >= 2) {
     // Diagonal group, four consecutive amplitudes per thread: a term's sign parity on the
     // shared high bits is computed once; the two low bits flip it by the uniform pattern
     // pat(z) (bit j set when popcount(j & z) is odd).

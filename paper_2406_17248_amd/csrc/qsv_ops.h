@@ -176,6 +176,13 @@ struct PauliGroupArgs {
   int32_t      col;           // first partial column (real part; imaginary part at col + 1)
   int32_t      ncols;
   int32_t      real_coeffs;   // 1 when every cim is 0 (the imaginary part is not accumulated)
+  // Diagonal groups over n >= 12 qubits (n_pats > 0): the terms sorted by their pattern on
+  // the 12 low qubits; pats[p] = pattern | (index of its first term) << 12, and the patterns
+  // whose bits 8-11 equal r are pats[rfirst[r] .. rfirst[r + 1]) (r = 0..15).
+  const uint32_t* pats;
+  const int32_t*  rfirst;
+  int32_t      n_pats;
 };
+constexpr int kPauliMaxPatterns = 256;
 
 }  // namespace qsv
