@@ -847,6 +847,7 @@ struct PassEmitter {
         op.gen = alloc(prim_size(p));
         plan.fills.push_back({F_PRIM_GEN, pi, 0, op.gen});
         prm = p.param;
+        if (p.type == P_DENSE1) op.gkind = p.gen == G_X ? GEN_X : p.gen == G_Y ? GEN_Y : GEN_GENERAL;
       }
       push(op, prm);
     }

@@ -525,7 +525,20 @@ __device__ __forceinline__ int spread_of(uint32_t reg, int k) {
 // 2x2 gate on register bit I.  Gates without local controls (the common case, a
 // wave-uniform test) run straight-line; controlled ones compute every pair and keep the
 // old values by select where a control bit is 0, so no lane-divergent branch is formed.
-template <int I, int NR, bool ADJ, typename C>
+// Re(conj(w) * g) in fp64
+template <typename C> __device__ __forceinline__ double re_conj_mul(C w, C g) {
+  return (double)w.x * (double)g.x + (double)w.y * (double)g.y;
+}
+// The adjoint gradient term of a slot pair, Im<w|G|v> over (k, k1): a general 2x2 G, or
+// k X / k Y without the multiplications by their zeros (k applied by the caller).
+template <int GK, typename C>
+__device__ __forceinline__ double grad_term(C w0, C w1, C v0, C v1, const C* G) {
+  if constexpr (GK == GEN_X) return im_conj_mul(w0, v1) + im_conj_mul(w1, v0);
+  else if constexpr (GK == GEN_Y) return re_conj_mul(w1, v0) - re_conj_mul(w0, v1);
+  else return im_conj_mul(w0, cdot2(G[0], v0, G[1], v1)) + im_conj_mul(w1, cdot2(G[2], v0, G[3], v1));
+}
+
+template <int I, int NR, bool ADJ, int GK, typename C>
 __device__ __forceinline__ void reg1(C* v, C* w, int jt, uint32_t reg, uint32_t lm, const C* U, bool grad,
                                      const C* G, double& acc) {
   if (lm == 0) {
@@ -535,7 +548,7 @@ __device__ __forceinline__ void reg1(C* v, C* w, int jt, uint32_t reg, uint32_t 
       const int k1 = k | (1 << I);
       if (ADJ) {
         double g = 0.0;
-        if (grad) g = im_conj_mul(w[k], cdot2(G[0], v[k], G[1], v[k1])) + im_conj_mul(w[k1], cdot2(G[2], v[k], G[3], v[k1]));
+        if (grad) g = grad_term<GK>(w[k], w[k1], v[k], v[k1], G);
         apply2(U[0], U[1], U[2], U[3], w[k], w[k1], g);
         apply2(U[0], U[1], U[2], U[3], v[k], v[k1], g);
         acc += g;
@@ -554,7 +567,7 @@ __device__ __forceinline__ void reg1(C* v, C* w, int jt, uint32_t reg, uint32_t 
     if (ADJ) {
       C m0 = w[k], m1 = w[k1];
       double g = 0.0;
-      if (grad) g = im_conj_mul(m0, cdot2(G[0], n0, G[1], n1)) + im_conj_mul(m1, cdot2(G[2], n0, G[3], n1));
+      if (grad) g = grad_term<GK>(m0, m1, n0, n1, G);
       apply2(U[0], U[1], U[2], U[3], m0, m1, g);
       acc += ok ? g : 0.0;
       const uint64_t okm = __builtin_amdgcn_ballot_w64(ok);
@@ -578,18 +591,34 @@ __device__ __forceinline__ void mat4(const C* M, const C* x, C* y) {
   }
 }
 
-template <int RB, bool ADJ, typename C>
-__device__ __forceinline__ void reg1_dispatch(int i, C* v, C* w, int jt, uint32_t reg, uint32_t lm, const C* U, bool grad,
-                                              const C* G, double& acc) {
+template <int RB, bool ADJ, int GK, typename C>
+__device__ __forceinline__ void reg1_slot(int i, C* v, C* w, int jt, uint32_t reg, uint32_t lm, const C* U,
+                                          bool grad, const C* G, double& acc) {
   constexpr int NR = 1 << RB;
   switch (i) {
-    case 0: reg1<0, NR, ADJ>(v, w, jt, reg, lm, U, grad, G, acc); break;
-    case 1: reg1<1, NR, ADJ>(v, w, jt, reg, lm, U, grad, G, acc); break;
-    case 2: reg1<2, NR, ADJ>(v, w, jt, reg, lm, U, grad, G, acc); break;
+    case 0: reg1<0, NR, ADJ, GK>(v, w, jt, reg, lm, U, grad, G, acc); break;
+    case 1: reg1<1, NR, ADJ, GK>(v, w, jt, reg, lm, U, grad, G, acc); break;
+    case 2: reg1<2, NR, ADJ, GK>(v, w, jt, reg, lm, U, grad, G, acc); break;
     default:
-      if constexpr (RB > 3) reg1<(RB > 3 ? 3 : 0), NR, ADJ>(v, w, jt, reg, lm, U, grad, G, acc);
+      if constexpr (RB > 3) reg1<(RB > 3 ? 3 : 0), NR, ADJ, GK>(v, w, jt, reg, lm, U, grad, G, acc);
       break;
   }
+}
+// Forward passes and gradient-free adjoint gates use the general form (its gradient
+// code is not reached); gradient-bearing adjoint gates with an X or Y generator get the
+// shorter gradient term, scaled by k once per op.
+template <int RB, bool ADJ, typename C>
+__device__ __forceinline__ void reg1_dispatch(int i, C* v, C* w, int jt, uint32_t reg, uint32_t lm, const C* U,
+                                              bool grad, int gkind, const C* G, double& acc) {
+  if (ADJ && grad && gkind != GEN_GENERAL) {
+    const double kf = gkind == GEN_X ? (double)G[1].x : (double)G[2].y;
+    double part = 0.0;
+    if (gkind == GEN_X) reg1_slot<RB, ADJ, GEN_X>(i, v, w, jt, reg, lm, U, true, G, part);
+    else reg1_slot<RB, ADJ, GEN_Y>(i, v, w, jt, reg, lm, U, true, G, part);
+    acc = __builtin_fma(kf, part, acc);
+    return;
+  }
+  reg1_slot<RB, ADJ, GEN_GENERAL>(i, v, w, jt, reg, lm, U, grad, G, acc);
 }
 
 // Fused 8x8 block on (lane bit 4, lane bit 5, slot bit I) with the matrix cores.  A lane
@@ -918,7 +947,7 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
 #pragma unroll
         for (int r = 0; r < 4; ++r) G[r] = ldc(T + gen + r);
       }
-      reg1_dispatch<RB, ADJ>(ld(&O->a), v, w, jt, reg_cur, lmask, U, grad, G, acc);
+      reg1_dispatch<RB, ADJ>(ld(&O->a), v, w, jt, reg_cur, lmask, U, grad, ADJ ? ld(&O->gkind) : 0, G, acc);
     } else if (on && type == OP_DENSE2) {
       // two-qubit dense gate on local bits a, b, applied to the tile staged in LDS (no
       // gradient: parameterized two-qubit rotations are lowered to RZZ with basis changes)

@@ -56,7 +56,12 @@ struct TileOp {
                        // ZZ: count+1 real weights in .x), -1 if no gradient here
   int32_t  pslot;      // adjoint: output column of the accumulated gradient (or -1)
   int32_t  flush;      // adjoint: reduce the accumulator into pslot after this op
+  int32_t  gkind;      // adjoint DENSE1: the generator's form (GEN_*), for a cheaper
+                       // gradient term than the general 2x2 product
 };
+// Generator forms of DENSE1 ops (k = the chain-rule factor, read from the generator table):
+// GEN_GENERAL: any 2x2; GEN_X: k X (ctab[gen + 1] = k); GEN_Y: k Y (ctab[gen + 2] = i k).
+enum GenForm : int32_t { GEN_GENERAL = 0, GEN_X = 1, GEN_Y = 2 };
 
 // One diagonal gate inside an OP_DIAG run.  The gate's qubits q0, q1 (q1 = -1 for one
 // qubit) and control mask are global positions; the phase applied to amplitude x is
