@@ -39,6 +39,7 @@ VALU_NONPACKED_TFLOPS = 78.6
 FLOP_PER_AMP_DENSE1 = 14
 METRIC = "state-vector HBM GB/s vs peak; adjoint grad evals/s vs parameter-shift"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_pass_brick30_traffic.txt")
+QAOA_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_pass_adjoint_qaoa24_traffic.txt")
 TRAFFIC_SOURCES = ["qsv_kernels.hip", "engine.cpp", "api.cpp"]
 
 
@@ -51,11 +52,11 @@ def sources_digest():
     return h.hexdigest()
 
 
-def committed_traffic(dtype):
-    """HBM bytes per fused-pass launch from the committed rocprofv3 counter summary, or
-    None when it is missing or the kernel, planner or launch sources changed since."""
+def committed_traffic(dtype, path=TRAFFIC_FILE):
+    """HBM bytes per launch of the profiled pass from a committed rocprofv3 counter summary,
+    or None when it is missing or the kernel, planner or launch sources changed since."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
     except OSError:
         return None
@@ -189,7 +190,8 @@ def qaoa_leg(Q, dtype, ps_sets, with_copy=False):
     peak = VALU_PEAK_TFLOPS[dtype]
     achieved = flop_launch / avg_s / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": None, "kernel": "tile_pass_rb adjoint (psi and lambda, reverse sweep)",
+            "traffic": committed_traffic(dtype, QAOA_TRAFFIC_FILE),
+            "kernel": "tile_pass_rb adjoint (psi and lambda, reverse sweep)",
             "launches_per_eval": launches, "avg_launch_ms": avg_s * 1e3,
             "algorithmic_flop_per_launch": flop_launch, "algorithmic_bytes_per_launch": bytes_launch,
             "hbm_GBs": bytes_launch / avg_s / 1e9, "hbm_frac": bytes_launch / avg_s / 1e9 / HBM_PEAK_GBS,
