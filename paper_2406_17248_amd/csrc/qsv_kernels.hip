@@ -988,45 +988,50 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
       apply_staged(v);
       if (ADJ) apply_staged(w);
     } else if (on && active && type == OP_DIAG && ob) {
+      // Slots two at a time, each pair walking the run's entries (scalar loads, cached):
+      // phases and generator weights for every slot at once would hold another register
+      // block and cut the number of resident waves.
       const int first = ld(&O->first), count = ld(&O->count);
-      C ph[NR];
-      double gw[NR];
 #pragma unroll
-      for (int k = 0; k < NR; ++k) { ph[k] = C{1, 0}; gw[k] = 0.0; }
-      uint32_t sm = 0;
-      for (int e = 0; e < count; ++e) {
-        const DiagEntry* d = A.diag + first + e;
-        const uint64_t ocm = ld(&d->ocmask);
-        if ((base & ocm) != ocm) continue;  // an outside control is 0 in this tile
-        const uint32_t lcm = ld(&d->lcmask);
-        if (ld(&d->kind) == DIAG_SIGN) {
-          const uint32_t tm = ld(&d->tmask);
-          if (((uint32_t)jt & tm) == tm) sm ^= ld(&d->kmask);
-        } else {
-          const int l0 = ld(&d->l0), l1 = ld(&d->l1), q0 = ld(&d->q0), q1 = ld(&d->q1);
-          const int mat = ld(&d->mat);
-          const int dg = ADJ ? ld(&d->gen) : -1;
+      for (int k0 = 0; k0 < NR; k0 += 2) {
+        C ph[2] = {C{1, 0}, C{1, 0}};
+        double gw[2] = {0.0, 0.0};
+        uint32_t sm = 0;
+        for (int e = 0; e < count; ++e) {
+          const DiagEntry* d = A.diag + first + e;
+          const uint64_t ocm = ld(&d->ocmask);
+          if ((base & ocm) != ocm) continue;  // an outside control is 0 in this tile
+          const uint32_t lcm = ld(&d->lcmask);
+          if (ld(&d->kind) == DIAG_SIGN) {
+            const uint32_t tm = ld(&d->tmask);
+            if (((uint32_t)jt & tm) == tm) sm ^= ld(&d->kmask);
+          } else {
+            const int l0 = ld(&d->l0), l1 = ld(&d->l1), q0 = ld(&d->q0), q1 = ld(&d->q1);
+            const int mat = ld(&d->mat);
+            const int dg = ADJ ? ld(&d->gen) : -1;
 #pragma unroll
-          for (int k = 0; k < NR; ++k) {
-            const int j = jt | spread_of<NR>(reg_cur, k);
-            if (((uint32_t)j & lcm) != lcm) continue;
-            const int idx = gbit(j, l0, q0) | (q1 >= 0 ? gbit(j, l1, q1) << 1 : 0);
-            ph[k] = cmul(ph[k], tab(mat + idx));
-            if (ADJ && dg >= 0) gw[k] += (double)tab(dg + idx).x;
+            for (int h = 0; h < 2; ++h) {
+              const int j = jt | spread_of<NR>(reg_cur, k0 + h);
+              if (((uint32_t)j & lcm) != lcm) continue;
+              const int idx = gbit(j, l0, q0) | (q1 >= 0 ? gbit(j, l1, q1) << 1 : 0);
+              ph[h] = cmul(ph[h], tab(mat + idx));
+              if (ADJ && dg >= 0) gw[h] += (double)tab(dg + idx).x;
+            }
           }
         }
-      }
 #pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        C p = ph[k];
-        flip_sign(p, (sm << (31 - k)) & 0x80000000u);
-        if (ADJ) {
-          double g = gw[k] * im_conj_mul(w[k], v[k]);
-          cmul_in(w[k], p, g);
-          cmul_in(v[k], p, g);
-          acc += g;
-        } else {
-          cmul_in(v[k], p);
+        for (int h = 0; h < 2; ++h) {
+          const int k = k0 + h;
+          C p = ph[h];
+          flip_sign(p, (sm << (31 - k)) & 0x80000000u);
+          if (ADJ) {
+            double g = gw[h] * im_conj_mul(w[k], v[k]);
+            cmul_in(w[k], p, g);
+            cmul_in(v[k], p, g);
+            acc += g;
+          } else {
+            cmul_in(v[k], p);
+          }
         }
       }
     } else if (on && active && type == OP_ZZ) {
