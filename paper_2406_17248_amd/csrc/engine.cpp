@@ -849,6 +849,8 @@ struct PassEmitter {
         prm = p.param;
         if (p.type == P_DENSE1) op.gkind = p.gen == G_X ? GEN_X : p.gen == G_Y ? GEN_Y : GEN_GENERAL;
       }
+      if (reg_index && !adjoint && op.type == OP_DENSE1 && op.lmask == 0)
+        op.plain = (1 + op.a) | (op.b ? kPlainSigns : 0);
       push(op, prm);
     }
   }

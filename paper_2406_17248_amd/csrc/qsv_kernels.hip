@@ -753,7 +753,7 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
   __shared__ double red[NT >= 64 ? NT / 64 : 1];
 
   const int tid = threadIdx.x;
-  const int m = A.m;
+  const int m = FULL ? MAXM : A.m;  // single-state launches require a full tile
   const int nloc = 1 << m;
   const bool active = FULL || tid < (nloc >> RB);
   const uint64_t TM = A.tile_mask;
@@ -864,6 +864,27 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
   double acc = 0.0;
   const TileOp* O = A.ops;
   for (int oi = 0; oi < A.n_ops; ++oi, ++O) {
+    // the short path: a one-qubit gate on a register slot, nothing else to decode
+    const uint64_t* hw = reinterpret_cast<const uint64_t*>(&O->plain);
+    const uint64_t h0 = ld(hw), h1 = ld(hw + 1);  // plain, mat | first, count
+    const int plain = (int)(uint32_t)h0;
+    if (!ADJ && plain) {
+      const int mat = (int)(uint32_t)(h0 >> 32);
+      C U[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) U[r] = ldc(T + mat + r);
+      if (active && (plain & kPlainSigns)) {
+        uint32_t touched;
+        const uint32_t sm = sign_slots(A.diag + (int)(uint32_t)h1, (int)(uint32_t)(h1 >> 32), base, (uint32_t)jt, touched);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          if (!((touched >> k) & 1u)) continue;
+          flip_sign(v[k], (sm << (31 - k)) & 0x80000000u);
+        }
+      }
+      if (active) reg1_slot<RB, ADJ, GEN_GENERAL>((plain & 7) - 1, v, w, jt, reg_cur, 0u, U, false, U, acc);
+      continue;
+    }
     const int type = ld(&O->type);
     const uint32_t lm_raw = ld(&O->lmask);
     bool on = true;
