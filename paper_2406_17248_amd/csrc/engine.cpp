@@ -767,6 +767,7 @@ struct PassEmitter {
     TileOp op{};
     op.type = OP_BLOCK;
     op.a = bslot;
+    op.plain = kPlainBlock | (1 + bslot);
     op.mat = alloc(128);
     op.gen = -1;
     op.pslot = -1;
@@ -849,8 +850,7 @@ struct PassEmitter {
         prm = p.param;
         if (p.type == P_DENSE1) op.gkind = p.gen == G_X ? GEN_X : p.gen == G_Y ? GEN_Y : GEN_GENERAL;
       }
-      if (reg_index && !adjoint && op.type == OP_DENSE1 && op.lmask == 0)
-        op.plain = (1 + op.a) | (op.b ? kPlainSigns : 0);
+      if (reg_index && op.type == OP_DENSE1 && op.lmask == 0) op.plain = (1 + op.a) | (op.b ? kPlainSigns : 0);
       push(op, prm);
     }
   }

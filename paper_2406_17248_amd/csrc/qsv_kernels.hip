@@ -864,189 +864,246 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
   double acc = 0.0;
   const TileOp* O = A.ops;
   for (int oi = 0; oi < A.n_ops; ++oi, ++O) {
-    // the short path: a one-qubit gate on a register slot, nothing else to decode
-    const uint64_t* hw = reinterpret_cast<const uint64_t*>(&O->plain);
-    const uint64_t h0 = ld(hw), h1 = ld(hw + 1);  // plain, mat | first, count
-    const int plain = (int)(uint32_t)h0;
-    if (!ADJ && plain) {
-      const int mat = (int)(uint32_t)(h0 >> 32);
-      C U[4];
+    // the record's first 16 bytes (adjoint: 32 bytes) in one scalar load
+    const uint64_t* hw = reinterpret_cast<const uint64_t*>(O);
+    const uint64_t h0 = ld(hw), h1 = ld(hw + 1), h2 = ADJ ? ld(hw + 2) : 0, h3 = ADJ ? ld(hw + 3) : 0;
+    const int plain = (int)(uint32_t)h0, mat = (int)(h0 >> 32);
+    const int first = (int)(uint32_t)h1, count = (int)(h1 >> 32);
+    const int gen = (int)(uint32_t)h2, pslot = (int)(h2 >> 32);
+    const int flush = (int)(uint32_t)h3, gkind = (int)(h3 >> 32);
+    if (plain) {
+      // the short path: a one-qubit gate on a register slot (after its sign run, if any)
+      // or a fused block, nothing else to decode
+      const int slot = (plain & 7) - 1;
+      if (!ADJ && (plain & kPlainBlock)) {
+        if (active) {
+          // the lane's four A operands: 4 consecutive reals at 4 * lane of the block's table
+          const R* ap = reinterpret_cast<const R*>(T + mat) + 4 * (tid & 63);
+          R am[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) U[r] = ldc(T + mat + r);
-      if (active && (plain & kPlainSigns)) {
+          for (int j = 0; j < 4; ++j) am[j] = ap[j];
+          block_dispatch<RB>(slot, v, am);
+        }
+      } else if (active) {
+        C U[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) U[r] = ldc(T + mat + r);
+        if (plain & kPlainSigns) {
+          uint32_t touched;
+          const uint32_t sm = sign_slots(A.diag + first, count, base, (uint32_t)jt, touched);
+#pragma unroll
+          for (int k = 0; k < NR; ++k) {
+            if (!((touched >> k) & 1u)) continue;
+            const uint32_t f = (sm << (31 - k)) & 0x80000000u;
+            flip_sign(v[k], f);
+            if (ADJ) flip_sign(w[k], f);
+          }
+        }
+        if (ADJ && gen >= 0) {
+          C G[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) G[r] = ldc(T + gen + r);
+          reg1_dispatch<RB, ADJ>(slot, v, w, jt, reg_cur, 0u, U, true, gkind, G, acc);
+        } else {
+          reg1_slot<RB, ADJ, GEN_GENERAL>(slot, v, w, jt, reg_cur, 0u, U, false, U, acc);
+        }
+      }
+    } else {
+      const int type = ld(&O->type);
+      const uint32_t lm_raw = ld(&O->lmask);
+      bool on = true;
+      if (lm_raw & kHasOutsideControls) {
+        const uint64_t omask = ld(&O->omask);
+        on = (base & omask) == omask;
+      }
+      const uint32_t lmask = lm_raw & ~kHasOutsideControls;
+      // sign flips only (Z, CZ, multi-controlled Z), alone (DIAG with b = 0) or ahead of a
+      // gate (DENSE1 with b = 1): the parity of the satisfied entries, as one bit per
+      // register slot (slot 0 holds the thread's own local index)
+      const int ob = ld(&O->b);
+      if (on && active && ((type == OP_DIAG && !ob) || (type == OP_DENSE1 && ob))) {
         uint32_t touched;
-        const uint32_t sm = sign_slots(A.diag + (int)(uint32_t)h1, (int)(uint32_t)(h1 >> 32), base, (uint32_t)jt, touched);
+        const uint32_t sm = sign_slots(A.diag + first, count, base, (uint32_t)jt, touched);
+        // slots no entry can reach are skipped (a wave-uniform test): an entry on a register
+        // bit reaches half of them
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
           if (!((touched >> k) & 1u)) continue;
-          flip_sign(v[k], (sm << (31 - k)) & 0x80000000u);
+          const uint32_t f = (sm << (31 - k)) & 0x80000000u;
+          flip_sign(v[k], f);
+          if (ADJ) flip_sign(w[k], f);
         }
       }
-      if (active) reg1_slot<RB, ADJ, GEN_GENERAL>((plain & 7) - 1, v, w, jt, reg_cur, 0u, U, false, U, acc);
-      continue;
-    }
-    const int type = ld(&O->type);
-    const uint32_t lm_raw = ld(&O->lmask);
-    bool on = true;
-    if (lm_raw & kHasOutsideControls) {
-      const uint64_t omask = ld(&O->omask);
-      on = (base & omask) == omask;
-    }
-    const uint32_t lmask = lm_raw & ~kHasOutsideControls;
-    // sign flips only (Z, CZ, multi-controlled Z), alone (DIAG with b = 0) or ahead of a
-    // gate (DENSE1 with b = 1): the parity of the satisfied entries, as one bit per
-    // register slot (slot 0 holds the thread's own local index)
-    const int ob = ld(&O->b);
-    if (on && active && ((type == OP_DIAG && !ob) || (type == OP_DENSE1 && ob))) {
-      uint32_t touched;
-      const uint32_t sm = sign_slots(A.diag + ld(&O->first), ld(&O->count), base, (uint32_t)jt, touched);
-      // slots no entry can reach are skipped (a wave-uniform test): an entry on a register
-      // bit reaches half of them
+      if (type == OP_REMAP || type == OP_XSWAP) {
+        // the new layout: register slot bits, thread bits, the thread's part of its indices
+        const uint32_t lr = (uint32_t)ld(&O->b);
+        const int jn = layout(ld(&O->omask));
+        const int sw_new = swz<S>(jn) * (int)sizeof(C);
+        if (type == OP_XSWAP) {
+          // one transposition per op, by cross-lane moves; every lane takes part (partners
+          // of active lanes are active)
+          const int code = mat & 255;
+          xswap_dispatch<RB>(code, v);
+          if (ADJ) xswap_dispatch<RB>(code, w);
+        } else {
+          int uo[NR], un[NR];
+          slot_offsets(reg_cur, uo);
+          slot_offsets(lr, un);
+          if (active) {
 #pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        if (!((touched >> k) & 1u)) continue;
-        const uint32_t f = (sm << (31 - k)) & 0x80000000u;
-        flip_sign(v[k], f);
-        if (ADJ) flip_sign(w[k], f);
-      }
-    }
-    if (type == OP_REMAP || type == OP_XSWAP) {
-      // the new layout: register slot bits, thread bits, the thread's part of its indices
-      const uint32_t lr = (uint32_t)ld(&O->b);
-      const int jn = layout(ld(&O->omask));
-      const int sw_new = swz<S>(jn) * (int)sizeof(C);
-      if (type == OP_XSWAP) {
-        // one transposition per op, by cross-lane moves; every lane takes part (partners
-        // of active lanes are active)
-        const int code = ld(&O->mat) & 255;
-        xswap_dispatch<RB>(code, v);
-        if (ADJ) xswap_dispatch<RB>(code, w);
-      } else {
-        int uo[NR], un[NR];
+            for (int k = 0; k < NR; ++k) lds_at(sw_cur ^ uo[k]) = v[k];
+          }
+          __syncthreads();
+          if (active) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) v[k] = lds_at(sw_new ^ un[k]);
+          }
+          if (ADJ) {
+            __syncthreads();
+            if (active) {
+#pragma unroll
+              for (int k = 0; k < NR; ++k) lds_at(sw_cur ^ uo[k]) = w[k];
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll
+              for (int k = 0; k < NR; ++k) w[k] = lds_at(sw_new ^ un[k]);
+            }
+          }
+          __syncthreads();
+        }
+        jt = jn;
+        reg_cur = lr;
+        sw_cur = sw_new;
+      } else if (on && active && type == OP_DENSE1) {
+        C U[4], G[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) U[r] = ldc(T + mat + r);
+        const bool grad = ADJ && gen >= 0;
+        if (grad) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) G[r] = ldc(T + gen + r);
+        }
+        reg1_dispatch<RB, ADJ>(ld(&O->a), v, w, jt, reg_cur, lmask, U, grad, ADJ ? gkind : 0, G, acc);
+      } else if (on && type == OP_DENSE2) {
+        // two-qubit dense gate on local bits a, b, applied to the tile staged in LDS (no
+        // gradient: parameterized two-qubit rotations are lowered to RZZ with basis changes)
+        const int a = ld(&O->a), bb = ld(&O->b);
+        const int lo = a < bb ? a : bb, hi = a < bb ? bb : a;
+        const uint32_t lm = lmask;
+        int uo[NR];
         slot_offsets(reg_cur, uo);
-        slot_offsets(lr, un);
-        if (active) {
+        auto apply_staged = [&](C (&reg)[NR]) {
+          if (active) {
 #pragma unroll
-          for (int k = 0; k < NR; ++k) lds_at(sw_cur ^ uo[k]) = v[k];
-        }
-        __syncthreads();
-        if (active) {
+            for (int k = 0; k < NR; ++k) lds_at(sw_cur ^ uo[k]) = reg[k];
+          }
+          __syncthreads();
+          for (int p = tid; p < (nloc >> 2); p += NT) {
+            const int t = insert_zero(insert_zero(p, lo), hi);
+            if (((uint32_t)t & lm) != lm) continue;
+            const int idx[4] = {t, t | (1 << a), t | (1 << bb), t | (1 << a) | (1 << bb)};
+            C x[4], y[4];
 #pragma unroll
-          for (int k = 0; k < NR; ++k) v[k] = lds_at(sw_new ^ un[k]);
-        }
-        if (ADJ) {
+            for (int r = 0; r < 4; ++r) x[r] = buf[swz<S>(idx[r])];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              y[r] = cdot2(ldc(T + mat + 4 * r), x[0], ldc(T + mat + 4 * r + 1), x[1]);
+              y[r] = cdot2(C{1, 0}, y[r], ldc(T + mat + 4 * r + 2), x[2]);
+              y[r] = cdot2(C{1, 0}, y[r], ldc(T + mat + 4 * r + 3), x[3]);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) buf[swz<S>(idx[r])] = y[r];
+          }
           __syncthreads();
           if (active) {
 #pragma unroll
-            for (int k = 0; k < NR; ++k) lds_at(sw_cur ^ uo[k]) = w[k];
+            for (int k = 0; k < NR; ++k) reg[k] = lds_at(sw_cur ^ uo[k]);
           }
           __syncthreads();
-          if (active) {
+        };
+        apply_staged(v);
+        if (ADJ) apply_staged(w);
+      } else if (on && active && type == OP_DIAG && ob) {
+        // Slots two at a time, each pair walking the run's entries (scalar loads, cached):
+        // phases and generator weights for every slot at once would hold another register
+        // block and cut the number of resident waves.
 #pragma unroll
-            for (int k = 0; k < NR; ++k) w[k] = lds_at(sw_new ^ un[k]);
-          }
-        }
-        __syncthreads();
-      }
-      jt = jn;
-      reg_cur = lr;
-      sw_cur = sw_new;
-    } else if (!ADJ && active && type == OP_BLOCK) {
-      // the lane's four A operands: 4 consecutive reals at 4 * lane of the block's table
-      const R* ap = reinterpret_cast<const R*>(T + ld(&O->mat)) + 4 * (tid & 63);
-      R a[4];
+        for (int k0 = 0; k0 < NR; k0 += 2) {
+          C ph[2] = {C{1, 0}, C{1, 0}};
+          double gw[2] = {0.0, 0.0};
+          uint32_t sm = 0;
+          for (int e = 0; e < count; ++e) {
+            const DiagEntry* d = A.diag + first + e;
+            const uint64_t ocm = ld(&d->ocmask);
+            if ((base & ocm) != ocm) continue;  // an outside control is 0 in this tile
+            const uint32_t lcm = ld(&d->lcmask);
+            if (ld(&d->kind) == DIAG_SIGN) {
+              const uint32_t tm = ld(&d->tmask);
+              if (((uint32_t)jt & tm) == tm) sm ^= ld(&d->kmask);
+            } else {
+              const int l0 = ld(&d->l0), l1 = ld(&d->l1), q0 = ld(&d->q0), q1 = ld(&d->q1);
+              const int mat = ld(&d->mat);
+              const int dg = ADJ ? ld(&d->gen) : -1;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) a[j] = ap[j];
-      block_dispatch<RB>(ld(&O->a), v, a);
-    } else if (on && active && type == OP_DENSE1) {
-      const int mat = ld(&O->mat), gen = ld(&O->gen);
-      C U[4], G[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) U[r] = ldc(T + mat + r);
-      const bool grad = ADJ && gen >= 0;
-      if (grad) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) G[r] = ldc(T + gen + r);
-      }
-      reg1_dispatch<RB, ADJ>(ld(&O->a), v, w, jt, reg_cur, lmask, U, grad, ADJ ? ld(&O->gkind) : 0, G, acc);
-    } else if (on && type == OP_DENSE2) {
-      // two-qubit dense gate on local bits a, b, applied to the tile staged in LDS (no
-      // gradient: parameterized two-qubit rotations are lowered to RZZ with basis changes)
-      const int a = ld(&O->a), bb = ld(&O->b), mat = ld(&O->mat);
-      const int lo = a < bb ? a : bb, hi = a < bb ? bb : a;
-      const uint32_t lm = lmask;
-      int uo[NR];
-      slot_offsets(reg_cur, uo);
-      auto apply_staged = [&](C (&reg)[NR]) {
-        if (active) {
-#pragma unroll
-          for (int k = 0; k < NR; ++k) lds_at(sw_cur ^ uo[k]) = reg[k];
-        }
-        __syncthreads();
-        for (int p = tid; p < (nloc >> 2); p += NT) {
-          const int t = insert_zero(insert_zero(p, lo), hi);
-          if (((uint32_t)t & lm) != lm) continue;
-          const int idx[4] = {t, t | (1 << a), t | (1 << bb), t | (1 << a) | (1 << bb)};
-          C x[4], y[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) x[r] = buf[swz<S>(idx[r])];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            y[r] = cdot2(ldc(T + mat + 4 * r), x[0], ldc(T + mat + 4 * r + 1), x[1]);
-            y[r] = cdot2(C{1, 0}, y[r], ldc(T + mat + 4 * r + 2), x[2]);
-            y[r] = cdot2(C{1, 0}, y[r], ldc(T + mat + 4 * r + 3), x[3]);
+              for (int h = 0; h < 2; ++h) {
+                const int j = jt | spread_of<NR>(reg_cur, k0 + h);
+                if (((uint32_t)j & lcm) != lcm) continue;
+                const int idx = gbit(j, l0, q0) | (q1 >= 0 ? gbit(j, l1, q1) << 1 : 0);
+                ph[h] = cmul(ph[h], tab(mat + idx));
+                if (ADJ && dg >= 0) gw[h] += (double)tab(dg + idx).x;
+              }
+            }
           }
 #pragma unroll
-          for (int r = 0; r < 4; ++r) buf[swz<S>(idx[r])] = y[r];
-        }
-        __syncthreads();
-        if (active) {
-#pragma unroll
-          for (int k = 0; k < NR; ++k) reg[k] = lds_at(sw_cur ^ uo[k]);
-        }
-        __syncthreads();
-      };
-      apply_staged(v);
-      if (ADJ) apply_staged(w);
-    } else if (on && active && type == OP_DIAG && ob) {
-      // Slots two at a time, each pair walking the run's entries (scalar loads, cached):
-      // phases and generator weights for every slot at once would hold another register
-      // block and cut the number of resident waves.
-      const int first = ld(&O->first), count = ld(&O->count);
-#pragma unroll
-      for (int k0 = 0; k0 < NR; k0 += 2) {
-        C ph[2] = {C{1, 0}, C{1, 0}};
-        double gw[2] = {0.0, 0.0};
-        uint32_t sm = 0;
-        for (int e = 0; e < count; ++e) {
-          const DiagEntry* d = A.diag + first + e;
-          const uint64_t ocm = ld(&d->ocmask);
-          if ((base & ocm) != ocm) continue;  // an outside control is 0 in this tile
-          const uint32_t lcm = ld(&d->lcmask);
-          if (ld(&d->kind) == DIAG_SIGN) {
-            const uint32_t tm = ld(&d->tmask);
-            if (((uint32_t)jt & tm) == tm) sm ^= ld(&d->kmask);
-          } else {
-            const int l0 = ld(&d->l0), l1 = ld(&d->l1), q0 = ld(&d->q0), q1 = ld(&d->q1);
-            const int mat = ld(&d->mat);
-            const int dg = ADJ ? ld(&d->gen) : -1;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const int j = jt | spread_of<NR>(reg_cur, k0 + h);
-              if (((uint32_t)j & lcm) != lcm) continue;
-              const int idx = gbit(j, l0, q0) | (q1 >= 0 ? gbit(j, l1, q1) << 1 : 0);
-              ph[h] = cmul(ph[h], tab(mat + idx));
-              if (ADJ && dg >= 0) gw[h] += (double)tab(dg + idx).x;
+          for (int h = 0; h < 2; ++h) {
+            const int k = k0 + h;
+            C p = ph[h];
+            flip_sign(p, (sm << (31 - k)) & 0x80000000u);
+            if (ADJ) {
+              double g = gw[h] * im_conj_mul(w[k], v[k]);
+              cmul_in(w[k], p, g);
+              cmul_in(v[k], p, g);
+              acc += g;
+            } else {
+              cmul_in(v[k], p);
             }
           }
         }
+      } else if (on && active && type == OP_ZZ) {
+        // c(x) = number of edges whose endpoints differ.  Edges come grouped by register
+        // class c; an edge of class c differs in slot k iff its thread/outside parity
+        // differs from the parity of (k & c), so with a_c = the class's edges whose
+        // thread/outside parity is odd, c(slot k) = sum_c a_c + sum_{c: k & c odd} (n_c - 2 a_c).
+        // classes are register-bit masks of at most two bits, listed by zz_class<RB>(i); the
+        // edge count of class i is byte i of (a, b, lmask)
+        const uint32_t cw[3] = {(uint32_t)ld(&O->a), (uint32_t)ld(&O->b), lm_raw};
+        const ZZEdge* ed = A.edges + first;
+        constexpr int NCLS = zz_classes<RB>();
+        int sum_a = 0, dcls[NCLS];
+        int e = 0;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int k = k0 + h;
-          C p = ph[h];
-          flip_sign(p, (sm << (31 - k)) & 0x80000000u);
+        for (int c = 0; c < NCLS; ++c) {
+          const int nc = (int)((cw[c >> 2] >> (8 * (c & 3))) & 255u);
+          int a_c = 0;
+          for (int i = 0; i < nc; ++i, ++e) {
+            const uint32_t tm = ld(&ed[e].tmask);
+            const uint64_t om = ld(&ed[e].omask);
+            a_c += (__popc(jt & tm) + __popcll(base & om)) & 1;
+          }
+          sum_a += a_c;
+          dcls[c] = nc - 2 * a_c;
+        }
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          int cnt = sum_a;
+#pragma unroll
+          for (int c = 1; c < NCLS; ++c)
+            if (__builtin_popcount(k & zz_class<RB>(c)) & 1) cnt += dcls[c];
+          const C p = tab(mat + cnt);
           if (ADJ) {
-            double g = gw[h] * im_conj_mul(w[k], v[k]);
+            double g = 0.0;
+            if (gen >= 0) g = (double)tab(gen + cnt).x * im_conj_mul(w[k], v[k]);
             cmul_in(w[k], p, g);
             cmul_in(v[k], p, g);
             acc += g;
@@ -1055,60 +1112,18 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
           }
         }
       }
-    } else if (on && active && type == OP_ZZ) {
-      // c(x) = number of edges whose endpoints differ.  Edges come grouped by register
-      // class c; an edge of class c differs in slot k iff its thread/outside parity
-      // differs from the parity of (k & c), so with a_c = the class's edges whose
-      // thread/outside parity is odd, c(slot k) = sum_c a_c + sum_{c: k & c odd} (n_c - 2 a_c).
-      // classes are register-bit masks of at most two bits, listed by zz_class<RB>(i); the
-      // edge count of class i is byte i of (a, b, lmask)
-      const int first = ld(&O->first), mat = ld(&O->mat), gen = ld(&O->gen);
-      const uint32_t cw[3] = {(uint32_t)ld(&O->a), (uint32_t)ld(&O->b), lm_raw};
-      const ZZEdge* ed = A.edges + first;
-      constexpr int NCLS = zz_classes<RB>();
-      int sum_a = 0, dcls[NCLS];
-      int e = 0;
-#pragma unroll
-      for (int c = 0; c < NCLS; ++c) {
-        const int nc = (int)((cw[c >> 2] >> (8 * (c & 3))) & 255u);
-        int a_c = 0;
-        for (int i = 0; i < nc; ++i, ++e) {
-          const uint32_t tm = ld(&ed[e].tmask);
-          const uint64_t om = ld(&ed[e].omask);
-          a_c += (__popc(jt & tm) + __popcll(base & om)) & 1;
-        }
-        sum_a += a_c;
-        dcls[c] = nc - 2 * a_c;
-      }
-#pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        int cnt = sum_a;
-#pragma unroll
-        for (int c = 1; c < NCLS; ++c)
-          if (__builtin_popcount(k & zz_class<RB>(c)) & 1) cnt += dcls[c];
-        const C p = tab(mat + cnt);
-        if (ADJ) {
-          double g = 0.0;
-          if (gen >= 0) g = (double)tab(gen + cnt).x * im_conj_mul(w[k], v[k]);
-          cmul_in(w[k], p, g);
-          cmul_in(v[k], p, g);
-          acc += g;
-        } else {
-          cmul_in(v[k], p);
-        }
-      }
     }
-    if (ADJ && ld(&O->flush)) {
+    if (ADJ && flush) {
       const double sv = wave_sum(acc);
       if (defer) {
-        if ((tid & 63) == 0) gsum[ld(&O->pslot) * NW + (tid >> 6)] = sv;
+        if ((tid & 63) == 0) gsum[pslot * NW + (tid >> 6)] = sv;
       } else {
         if ((tid & 63) == 0) red[tid >> 6] = sv;
         __syncthreads();
         if (tid == 0) {
           double s = 0.0;
           for (int q = 0; q < NW; ++q) s += red[q];
-          A.partials[((int64_t)b * A.n_pslots + ld(&O->pslot)) * A.n_tiles + (int64_t)tile] = s;
+          A.partials[((int64_t)b * A.n_pslots + pslot) * A.n_tiles + (int64_t)tile] = s;
         }
         __syncthreads();
       }

@@ -45,29 +45,28 @@ enum OpType : int32_t {
 constexpr uint32_t kHasOutsideControls = 0x80000000u;
 
 struct TileOp {
-  // Register-blocked forward passes: a one-qubit gate on a register slot without controls,
+  // Register-blocked passes: a one-qubit gate on a register slot without controls,
   // optionally after a run of sign flips (kPlainSigns), has plain = 1 + slot (| kPlainSigns);
-  // the kernel reads the first four fields at once and skips decoding the rest.  0 for
-  // every other op.
+  // a fused block has plain = kPlainBlock | (1 + slot).  The kernel reads the first eight
+  // fields at once and decodes nothing else for these ops.  0 for every other op.
   int32_t  plain;
   int32_t  mat;        // ctab offset of the matrix (DENSE) or phase table (ZZ)
   int32_t  first;      // DIAG / ZZ / sign runs: first entry
   int32_t  count;      // DIAG / ZZ / sign runs: number of entries
-  int32_t  type;
-  int32_t  a, b;       // local target bits (DENSE1 / DENSE2)
-  uint32_t lmask;      // controls on local bits, in j-space: apply where (j & lmask) == lmask
-  uint64_t omask;      // controls on bits outside the tile: apply iff (base & omask) == omask
   int32_t  gen;        // adjoint: ctab offset of the scaled generator (DENSE: 4/16 entries,
                        // ZZ: count+1 real weights in .x), -1 if no gradient here
   int32_t  pslot;      // adjoint: output column of the accumulated gradient (or -1)
   int32_t  flush;      // adjoint: reduce the accumulator into pslot after this op
   int32_t  gkind;      // adjoint DENSE1: the generator's form (GEN_*), for a cheaper
                        // gradient term than the general 2x2 product
+  int32_t  type;
+  int32_t  a, b;       // local target bits (DENSE1 / DENSE2)
+  uint32_t lmask;      // controls on local bits, in j-space: apply where (j & lmask) == lmask
+  uint64_t omask;      // controls on bits outside the tile: apply iff (base & omask) == omask
 };
-constexpr int32_t kPlainSigns = 8;
-static_assert(offsetof(TileOp, plain) == 0 && offsetof(TileOp, mat) == 4 && offsetof(TileOp, first) == 8 &&
-                  offsetof(TileOp, count) == 12 && alignof(TileOp) == 8,
-              "plain, mat, first and count form the record's first 16 bytes");
+constexpr int32_t kPlainSigns = 8, kPlainBlock = 16;
+static_assert(offsetof(TileOp, plain) == 0 && offsetof(TileOp, gkind) == 28 && alignof(TileOp) == 8,
+              "plain .. gkind form the record's first 32 bytes");
 // Generator forms of DENSE1 ops (k = the chain-rule factor, read from the generator table):
 // GEN_GENERAL: any 2x2; GEN_X: k X (ctab[gen + 1] = k); GEN_Y: k Y (ctab[gen + 2] = i k).
 enum GenForm : int32_t { GEN_GENERAL = 0, GEN_X = 1, GEN_Y = 2 };
