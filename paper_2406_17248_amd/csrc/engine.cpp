@@ -30,6 +30,19 @@ bool mat_is_diagonal(const qsv_circuit* c, const qsv_gate& g) {
   return true;
 }
 
+// A MAT1 matrix that is unitary to rounding (the split of one-qubit gates into phases and a
+// real matrix reproduces only unitary matrices).
+bool mat1_is_unitary(const qsv_circuit* c, const qsv_gate& g) {
+  const double* m = c->matrices + 2 * g.matrix_offset;
+  const cplx u[4] = {cplx(m[0], m[1]), cplx(m[2], m[3]), cplx(m[4], m[5]), cplx(m[6], m[7])};
+  for (int r = 0; r < 2; ++r)
+    for (int k = 0; k < 2; ++k) {
+      const cplx e = u[2 * r] * std::conj(u[2 * k]) + u[2 * r + 1] * std::conj(u[2 * k + 1]);
+      if (std::abs(e - (r == k ? 1.0 : 0.0)) > 4e-15) return false;
+    }
+  return true;
+}
+
 bool kind_is_diagonal(const qsv_circuit* c, const qsv_gate& g) {
   switch (g.kind) {
     case QSV_GATE_Z: case QSV_GATE_S: case QSV_GATE_SDG: case QSV_GATE_T: case QSV_GATE_TDG:
@@ -272,8 +285,11 @@ PlanOptions state_plan_options(int32_t dtype, int32_t n, int32_t tile, int32_t a
   // 2 / 2.5 / 3 / 3.5 on the brick and QAOA circuits.  complex128: fp64 matrix and vector
   // rates are equal, so a block costs about four gates, but the matrix cores run beside the
   // vector ALU's other work; 4.5 is the best of 3.5 / 4.5 / 5.5 / none (brick: -7 %).
-  o.blocks = !adjoint;
-  o.block_min_gates = dtype == QSV_C64 ? 3.0 : 4.5;
+  o.blocks = !adjoint && dtype == QSV_C64;
+  o.block_min_gates = 3.0;
+  // complex128 forward passes split one-qubit gates instead: a phase and a real 2x2 matrix
+  // cost 12 vector instructions per amplitude pair instead of 16, more than a block saves
+  o.split = !adjoint && dtype == QSV_C128;
   return o;
 }
 
@@ -662,6 +678,7 @@ struct PassEmitter {
   int loc[64];
   std::vector<int32_t> op_param;  // gradient parameter of each op of the pass (-1 none)
   bool rb = false;                // register-blocked pass
+  const std::vector<char>* chain = nullptr;  // per primitive: 0, 1 split, 2 last of a chain
   RbLayout lay;                   // register-blocked passes: the current register layout
 
   int alloc(int count) {
@@ -840,8 +857,10 @@ struct PassEmitter {
       op.lmask = local_mask(p.cmask & T);
       op.omask = p.cmask & ~T;
       if (reg_index && op.omask) op.lmask |= kHasOutsideControls;
+      const int ch = (chain && reg_index && p.type == P_DENSE1) ? (*chain)[pi] : 0;
       op.mat = alloc(prim_size(p));
-      plan.fills.push_back({F_PRIM_MATRIX, pi, 0, op.mat});
+      if (ch) plan.fills.push_back({F_GATE_CHAIN, pi, ch == 1 ? 1 : 0, op.mat});
+      else plan.fills.push_back({F_PRIM_MATRIX, pi, 0, op.mat});
       int32_t prm = -1;
       if (adjoint && p.gen != G_NONE) {
         if (reg_index && p.type == P_DENSE2) fail(QSV_EINVAL, "internal: gradient on an LDS two-qubit op");
@@ -850,7 +869,9 @@ struct PassEmitter {
         prm = p.param;
         if (p.type == P_DENSE1) op.gkind = p.gen == G_X ? GEN_X : p.gen == G_Y ? GEN_Y : GEN_GENERAL;
       }
-      if (reg_index && op.type == OP_DENSE1 && op.lmask == 0) op.plain = (1 + op.a) | (op.b ? kPlainSigns : 0);
+      if (reg_index && op.type == OP_DENSE1 && op.lmask == 0)
+        op.plain = (1 + op.a) | (op.b ? kPlainSigns : 0) | (ch == 1 ? kPlainSplit : 0);
+      if (ch && !op.plain) fail(QSV_EINVAL, "internal: phase chain through a decoded gate");
       push(op, prm);
     }
   }
@@ -1050,6 +1071,44 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
   bool moved = false;
   for (int p = 0; p < P; ++p) moved |= lay[p] != lay[p + 1];
   plan.relayout = relay && moved;  // else every pass runs in place
+  // register rounds of every pass (fused-block passes plan rounds of three qubits, the block
+  // size)
+  std::vector<std::vector<Pass>> pass_rounds(P);
+  if (rb)
+    for (int pi = 0; pi < P; ++pi) {
+      const bool use_blocks = opt.blocks && !adjoint && passes[pi].m - reg_bits >= 6;
+      pass_rounds[pi] = plan_rounds(plan.prims, passes[pi].prims, passes[pi].tile_mask, use_blocks ? 3 : reg_bits);
+    }
+  // Phase chains: an uncontrolled one-qubit gate whose qubit's next non-diagonal primitive
+  // (in execution order, across passes) is again an uncontrolled one-qubit gate runs as
+  // diag(1, e^{i phi}) then a real 2x2 matrix; the remaining left diagonal commutes with
+  // everything up to that next gate, whose matrix absorbs it.  A chain's last gate stays
+  // dense.
+  std::vector<char> chain(plan.prims.size(), 0);
+  if (rb && opt.split && !adjoint && !opt.blocks) {
+    auto splittable = [&](int32_t i) {
+      const Prim& pr = plan.prims[i];
+      if (pr.type != P_DENSE1 || pr.cmask != 0) return false;
+      const qsv_gate& g = c->gates[pr.gate];
+      return pr.recipe != M_GATE || g.kind != QSV_GATE_MAT1 || mat1_is_unitary(c, g);
+    };
+    std::vector<int32_t> last(n, -1);  // each qubit's previous non-diagonal primitive
+    for (int pi = 0; pi < P; ++pi)
+      for (const Pass& rd : pass_rounds[pi])
+        for (int32_t i : rd.prims) {
+          uint64_t nd = plan.prims[i].nondiag;
+          while (nd) {
+            const int q = __builtin_ctzll(nd);
+            nd &= nd - 1;
+            const int32_t prev = last[q];
+            if (prev >= 0 && splittable(prev) && splittable(i)) {
+              chain[prev] = 1;
+              if (!chain[i]) chain[i] = 2;
+            }
+            last[q] = i;
+          }
+        }
+  }
   for (int pi = 0; pi < P; ++pi) {
     const Pass& ps = passes[pi];
     DevPass dp{};
@@ -1073,7 +1132,8 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
       // whose dense work is all uncontrolled one-qubit gates as blocks; other rounds stay
       // register rounds
       const bool use_blocks = opt.blocks && !adjoint && ps.m - r >= 6;
-      const std::vector<Pass> rounds = plan_rounds(plan.prims, ps.prims, ps.tile_mask, use_blocks ? 3 : r);
+      const std::vector<Pass>& rounds = pass_rounds[pi];
+      em.chain = &chain;
       const int32_t top = ((1 << r) - 1) << (ps.m - r);  // load/store layout
       const int R = (int)rounds.size();
       // local bits each round needs in registers (0: the round has no one-qubit dense gate)
@@ -1424,6 +1484,7 @@ std::string structure_key(const qsv_circuit* c, bool adjoint, const PlanOptions&
     int32_t rec[8] = {g.kind, g.targets[0], kNTargets[g.kind] == 2 ? g.targets[1] : -1, -1, -1, -1, 0, 0};
     for (int a = 0; a < kNAngles[g.kind]; ++a) rec[3 + a] = g.param_index[a];
     if (g.kind == QSV_GATE_MAT1 || g.kind == QSV_GATE_MAT2) rec[6] = mat_is_diagonal(c, g) ? 1 : 0;
+    if (g.kind == QSV_GATE_MAT1 && mat1_is_unitary(c, g)) rec[6] |= 2;
     if (g.kind == QSV_GATE_RZZ && i > 0 && c->gates[i - 1].kind == QSV_GATE_RZZ)
       rec[7] = same_binding(g, c->gates[i - 1]) ? 1 : 0;
     if (g.kind == QSV_GATE_RZZ || (kNAngles[g.kind] > 0 && g.param_index[0] >= 0)) {
@@ -1502,14 +1563,66 @@ static void block_matrix(const Plan& p, const qsv_circuit* c, const std::vector<
   }
 }
 
+void split_gate(const cplx* M, cplx* left, cplx* out) {
+  // M = diag(l0, l1) [[c, -s], [s, c]] diag(1, e^{i phi}) for unitary M: c = |M00| = |M11|,
+  // s = |M10| = |M01|; each phase comes from an entry of modulus at least 1/sqrt(2) where
+  // one exists, so rounding stays at the level of M's own.
+  const double a = std::abs(M[0]), b = std::abs(M[2]), nrm = std::hypot(a, b);
+  const double cs = a / nrm, sn = b / nrm;
+  cplx l0, l1, ph(1.0, 0.0);
+  auto unit = [](cplx z) { return z / std::abs(z); };
+  if (a >= b) {
+    l0 = unit(M[0]);
+    if (b > 0.0) {
+      l1 = unit(M[2]);
+      ph = unit(M[3] / l1);
+    } else {
+      l1 = unit(M[3]);
+    }
+  } else {
+    l1 = unit(M[2]);
+    if (a > 0.0) {
+      l0 = unit(M[0]);
+      ph = unit(-M[1] / l0);
+    } else {
+      l0 = unit(-M[1]);
+    }
+  }
+  left[0] = l0;
+  left[1] = l1;
+  out[0] = cplx(cs, -sn);  // row 0 of the real matrix
+  out[1] = cplx(sn, cs);   // row 1
+  out[2] = ph;
+}
+
 void bind_ctab(const Plan& p, const qsv_circuit* c, const double* params, const AngleOverride* ov, int n_ov,
                cplx* out) {
   std::vector<double> ang(3 * c->n_gates);
   for (size_t i = 0; i < c->n_gates; ++i) gate_angles(c->gates[i], params, &ang[3 * i]);
   for (int k = 0; k < n_ov; ++k) ang[3 * ov[k].gate + ov[k].slot] = ov[k].angle;
+  // phase chains: the left diagonal each qubit carries to its next gate
+  std::vector<cplx> carry(2 * (size_t)c->n_qubits, cplx(1.0, 0.0));
   for (const Fill& f : p.fills) {
     cplx* dst = out + f.offset;
     switch (f.kind) {
+      case F_GATE_CHAIN: {
+        const Prim& pr = p.prims[f.prim];
+        cplx M[4];
+        prim_numbers(pr, c, &ang[3 * pr.gate], M);
+        cplx* cq = &carry[2 * (size_t)pr.q0];
+        for (int r = 0; r < 2; ++r) {
+          M[2 * r] *= cq[0];
+          M[2 * r + 1] *= cq[1];
+        }
+        if (f.count) {
+          split_gate(M, cq, dst);
+          dst[3] = 0.0;
+        } else {
+          for (int e = 0; e < 4; ++e) dst[e] = M[e];
+          cq[0] = cq[1] = cplx(1.0, 0.0);
+        }
+        break;
+      }
       case F_PRIM_MATRIX: {
         const Prim& pr = p.prims[f.prim];
         prim_numbers(pr, c, &ang[3 * pr.gate], dst);

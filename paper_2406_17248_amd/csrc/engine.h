@@ -70,6 +70,10 @@ enum FillKind : int32_t {
   F_ZZ_GEN,           // coeff * (E - 2c) as real weights
   F_BLOCK,            // the product of a fused block's primitives as matrix-core operands
                       // (Fill::prim indexes Plan::blocks; 128 entries)
+  F_GATE_CHAIN,       // a one-qubit gate of a phase chain (Plan::split): its matrix times the
+                      // phase its qubit carries from the previous gate of the chain; count = 1:
+                      // split into (real matrix, phase), the left phase carried on, count = 0:
+                      // the chain's last gate, dense (4 entries either way)
 };
 struct Fill {
   int32_t kind;
@@ -183,6 +187,10 @@ struct PlanOptions {
                               // three-qubit rounds into 8x8 blocks on the matrix cores
   double  block_min_gates = 3.0;  // ... keeping a round's blocks when they average this many
                                   // one-qubit gates
+  bool    split = false;      // forward register-blocked plans without blocks: uncontrolled
+                              // one-qubit gates followed on their qubit by another such gate
+                              // run as a phase and a real 2x2 matrix; the rest of the gate (a
+                              // diagonal) is carried into the qubit's next gate
 };
 
 // Block index bit b of an 8x8 fused block and the real 16x16 matrix-core operands: the real
@@ -192,6 +200,10 @@ struct PlanOptions {
 // (complex64: accumulator row 4q + v holds real row q + 4v; complex128: row r holds row r).
 // out receives 256 reals, lane-major (lane l's four values at 4l).
 void block_operands(const cplx* M8, int dtype, double* out);
+
+// A unitary 2x2 M (row-major) as diag(left[0], left[1]) R diag(1, out[2]) with R real: out[0] =
+// (R00, R01) and out[1] = (R10, R11) as complex pairs of reals.
+void split_gate(const cplx* M, cplx* left, cplx* out);
 
 // Default tile widths of forward and adjoint plans, measured on the 30-qubit brick circuit
 // (forward) and the 24-qubit QAOA batch (adjoint): wider tiles save passes but need more

@@ -98,6 +98,27 @@ __device__ __forceinline__ void apply2(C u00, C u01, C u10, C u11, C& a0, C& a1,
   a1.x = fma_s(u11.x, a1.x, p1r);
   a1.y = fma_s(u11.x, a1.y, p1i);
 }
+// a1 <- a1 * p, then (a0, a1) <- (r0.x a0 + r0.y a1, r1.x a0 + r1.y a1) with real r, in place
+// (p and r wave-uniform): a phase and a real 2x2 matrix, 12 instructions per pair
+template <typename C>
+__device__ __forceinline__ void apply2split(C r0, C r1, C p, C& a0, C& a1) {
+  {
+    auto pr = -a1.y * p.y;
+    auto pi = a1.x * p.y;
+    order(pr, pi);
+    a1.x = fma_s(p.x, a1.x, pr);
+    a1.y = fma_s(p.x, a1.y, pi);
+  }
+  auto p0r = r0.y * a1.x;
+  auto p0i = r0.y * a1.y;
+  auto p1r = r1.x * a0.x;
+  auto p1i = r1.x * a0.y;
+  order(p0r, p0i, p1r, p1i);
+  a0.x = fma_s(r0.x, a0.x, p0r);
+  a0.y = fma_s(r0.x, a0.y, p0i);
+  a1.x = fma_s(r1.y, a1.x, p1r);
+  a1.y = fma_s(r1.y, a1.y, p1i);
+}
 // a <- a * p in place (p per lane), with an optional `pin` as above
 template <typename C, typename... Pin> __device__ __forceinline__ void cmul_in(C& a, C p, Pin&... pin) {
   auto pr = -a.y * p.y;
@@ -538,9 +559,17 @@ __device__ __forceinline__ double grad_term(C w0, C w1, C v0, C v1, const C* G) 
   else return im_conj_mul(w0, cdot2(G[0], v0, G[1], v1)) + im_conj_mul(w1, cdot2(G[2], v0, G[3], v1));
 }
 
-template <int I, int NR, bool ADJ, int GK, typename C>
+template <int I, int NR, bool ADJ, int GK, typename C, bool SPLIT = false>
 __device__ __forceinline__ void reg1(C* v, C* w, int jt, uint32_t reg, uint32_t lm, const C* U, bool grad,
                                      const C* G, double& acc) {
+  if (SPLIT) {  // forward, uncontrolled
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      if (k & (1 << I)) continue;
+      apply2split(U[0], U[1], U[2], v[k], v[k | (1 << I)]);
+    }
+    return;
+  }
   if (lm == 0) {
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
@@ -591,16 +620,16 @@ __device__ __forceinline__ void mat4(const C* M, const C* x, C* y) {
   }
 }
 
-template <int RB, bool ADJ, int GK, typename C>
+template <int RB, bool ADJ, int GK, typename C, bool SPLIT = false>
 __device__ __forceinline__ void reg1_slot(int i, C* v, C* w, int jt, uint32_t reg, uint32_t lm, const C* U,
                                           bool grad, const C* G, double& acc) {
   constexpr int NR = 1 << RB;
   switch (i) {
-    case 0: reg1<0, NR, ADJ, GK>(v, w, jt, reg, lm, U, grad, G, acc); break;
-    case 1: reg1<1, NR, ADJ, GK>(v, w, jt, reg, lm, U, grad, G, acc); break;
-    case 2: reg1<2, NR, ADJ, GK>(v, w, jt, reg, lm, U, grad, G, acc); break;
+    case 0: reg1<0, NR, ADJ, GK, C, SPLIT>(v, w, jt, reg, lm, U, grad, G, acc); break;
+    case 1: reg1<1, NR, ADJ, GK, C, SPLIT>(v, w, jt, reg, lm, U, grad, G, acc); break;
+    case 2: reg1<2, NR, ADJ, GK, C, SPLIT>(v, w, jt, reg, lm, U, grad, G, acc); break;
     default:
-      if constexpr (RB > 3) reg1<(RB > 3 ? 3 : 0), NR, ADJ, GK>(v, w, jt, reg, lm, U, grad, G, acc);
+      if constexpr (RB > 3) reg1<(RB > 3 ? 3 : 0), NR, ADJ, GK, C, SPLIT>(v, w, jt, reg, lm, U, grad, G, acc);
       break;
   }
 }
@@ -904,6 +933,8 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
 #pragma unroll
           for (int r = 0; r < 4; ++r) G[r] = ldc(T + gen + r);
           reg1_dispatch<RB, ADJ>(slot, v, w, jt, reg_cur, 0u, U, true, gkind, G, acc);
+        } else if (!ADJ && (plain & kPlainSplit)) {
+          reg1_slot<RB, ADJ, GEN_GENERAL, C, true>(slot, v, w, jt, reg_cur, 0u, U, false, U, acc);
         } else {
           reg1_slot<RB, ADJ, GEN_GENERAL>(slot, v, w, jt, reg_cur, 0u, U, false, U, acc);
         }

@@ -46,9 +46,11 @@ constexpr uint32_t kHasOutsideControls = 0x80000000u;
 
 struct TileOp {
   // Register-blocked passes: a one-qubit gate on a register slot without controls,
-  // optionally after a run of sign flips (kPlainSigns), has plain = 1 + slot (| kPlainSigns);
-  // a fused block has plain = kPlainBlock | (1 + slot).  The kernel reads the first eight
-  // fields at once and decodes nothing else for these ops.  0 for every other op.
+  // optionally after a run of sign flips (kPlainSigns), has plain = 1 + slot (| kPlainSigns,
+  // | kPlainSplit when its matrix is given as a phase on the slot's 1 half followed by a
+  // real 2x2 matrix: ctab[mat] = (R00, R01), ctab[mat + 1] = (R10, R11), ctab[mat + 2] = the
+  // phase); a fused block has plain = kPlainBlock | (1 + slot).  The kernel reads the first
+  // eight fields at once and decodes nothing else for these ops.  0 for every other op.
   int32_t  plain;
   int32_t  mat;        // ctab offset of the matrix (DENSE) or phase table (ZZ)
   int32_t  first;      // DIAG / ZZ / sign runs: first entry
@@ -64,7 +66,7 @@ struct TileOp {
   uint32_t lmask;      // controls on local bits, in j-space: apply where (j & lmask) == lmask
   uint64_t omask;      // controls on bits outside the tile: apply iff (base & omask) == omask
 };
-constexpr int32_t kPlainSigns = 8, kPlainBlock = 16;
+constexpr int32_t kPlainSigns = 8, kPlainBlock = 16, kPlainSplit = 32;
 static_assert(offsetof(TileOp, plain) == 0 && offsetof(TileOp, gkind) == 28 && alignof(TileOp) == 8,
               "plain .. gkind form the record's first 32 bytes");
 // Generator forms of DENSE1 ops (k = the chain-rule factor, read from the generator table):

@@ -11,7 +11,11 @@
 // cross-lane transposition) is a bijection of the tile's local bits whose transpositions
 // name valid slot and lane bits and lead to the layout the op states, and every fused block's
 // matrix-core operands decode to the real form of a complex matrix, unitary when its gates
-// are (every kind but the explicit matrices, which this fuzzer draws at random).
+// are (every kind but the explicit matrices, which this fuzzer draws at random, a third of
+// them unitary).  One-qubit gates split into a phase and a real matrix (complex128 forward
+// plans): split_gate reproduces random and edge-case unitaries, and along each qubit the
+// product of what the kernel applies (split gates, then the chain's dense last gate) equals
+// the product of the gates' own matrices.
 // Exit status 0 when every check holds.
 #include <algorithm>
 #include <cmath>
@@ -31,6 +35,25 @@ struct Circ {
   std::vector<double> mats;
   qsv_circuit c{};
 };
+
+// A random 2x2 unitary: Gram-Schmidt on two complex Gaussian columns, times a random phase.
+static void random_unitary(std::mt19937& rng, cplx* m) {
+  std::normal_distribution<double> g(0.0, 1.0);
+  cplx a0(g(rng), g(rng)), a1(g(rng), g(rng)), b0(g(rng), g(rng)), b1(g(rng), g(rng));
+  const double na = std::sqrt(std::norm(a0) + std::norm(a1));
+  a0 /= na;
+  a1 /= na;
+  const cplx pr = std::conj(a0) * b0 + std::conj(a1) * b1;
+  b0 -= pr * a0;
+  b1 -= pr * a1;
+  const double nb = std::sqrt(std::norm(b0) + std::norm(b1));
+  b0 /= nb;
+  b1 /= nb;
+  m[0] = a0;
+  m[1] = b0;
+  m[2] = a1;
+  m[3] = b1;
+}
 
 static void random_circuit(Circ& k, int n, int n_gates, int n_params, std::mt19937& rng) {
   std::uniform_int_distribution<int> kind_d(0, QSV_GATE_KIND_COUNT - 1), q_d(0, n - 1), pi_d(0, n_params - 1);
@@ -64,12 +87,21 @@ static void random_circuit(Circ& k, int n, int n_gates, int n_params, std::mt199
     if (g.kind == QSV_GATE_MAT1 || g.kind == QSV_GATE_MAT2) {
       const int d = g.kind == QSV_GATE_MAT1 ? 2 : 4;
       g.matrix_offset = (int64_t)(k.mats.size() / 2);
-      const bool diag = rng() % 3 == 0;  // diagonal matrices take the diagonal path
-      for (int r = 0; r < d; ++r)
-        for (int cc = 0; cc < d; ++cc) {
-          k.mats.push_back(diag && r != cc ? 0.0 : u(rng));
-          k.mats.push_back(diag && r != cc ? 0.0 : u(rng));
+      const int form = (int)(rng() % 3);  // 0: diagonal (the diagonal path), 1: random, 2: unitary
+      if (form == 2 && d == 2) {
+        cplx h[4];
+        random_unitary(rng, h);
+        for (const cplx& z : h) {
+          k.mats.push_back(z.real());
+          k.mats.push_back(z.imag());
         }
+      } else {
+        for (int r = 0; r < d; ++r)
+          for (int cc = 0; cc < d; ++cc) {
+            k.mats.push_back(form == 0 && r != cc ? 0.0 : u(rng));
+            k.mats.push_back(form == 0 && r != cc ? 0.0 : u(rng));
+          }
+      }
     }
     k.gates.push_back(g);
   }
@@ -77,6 +109,95 @@ static void random_circuit(Circ& k, int n, int n_gates, int n_params, std::mt199
 }
 
 static int g_unitary_blocks = 0;  // fused blocks whose unitarity was checked
+static int g_split_gates = 0;     // split gates whose chain products were checked
+
+static void mul2(const cplx* a, const cplx* b, cplx* out) {  // out = a b
+  cplx t[4];
+  for (int r = 0; r < 2; ++r)
+    for (int k = 0; k < 2; ++k) t[2 * r + k] = a[2 * r] * b[k] + a[2 * r + 1] * b[2 + k];
+  for (int i = 0; i < 4; ++i) out[i] = t[i];
+}
+
+// M = diag(l) R diag(1, ph) for random unitaries and unitaries with a zero or tiny entry.
+static int check_split_gate(std::mt19937& rng) {
+  std::vector<std::vector<cplx>> cases;
+  for (int t = 0; t < 2000; ++t) {
+    cplx m[4];
+    random_unitary(rng, m);
+    cases.push_back({m[0], m[1], m[2], m[3]});
+  }
+  const cplx e1 = std::polar(1.0, 0.7), e2 = std::polar(1.0, -2.1);
+  for (double eps : {0.0, 1e-300, 1e-12, 1e-6}) {
+    const double c = std::sqrt(1.0 - eps * eps);
+    cases.push_back({e1 * c, -e2 * eps, std::conj(e2) * eps * e1 * e2, std::conj(e1) * c * e1 * e2});
+    cases.push_back({e1 * eps, -e2 * c, std::conj(e2) * c * e1 * e2, std::conj(e1) * eps * e1 * e2});
+  }
+  for (const auto& M : cases) {
+    // the split reproduces M to rounding plus M's own distance from unitarity
+    double un = 0.0;
+    for (int r = 0; r < 2; ++r)
+      for (int k = 0; k < 2; ++k)
+        un = std::max(un, std::abs(M[2 * r] * std::conj(M[2 * k]) + M[2 * r + 1] * std::conj(M[2 * k + 1]) -
+                                   (r == k ? 1.0 : 0.0)));
+    cplx left[2], out[3];
+    split_gate(M.data(), left, out);
+    const cplx E[4] = {left[0] * out[0].real(), left[0] * out[0].imag() * out[2], left[1] * out[1].real(),
+                       left[1] * out[1].imag() * out[2]};
+    for (int i = 0; i < 4; ++i)
+      if (std::abs(E[i] - M[i]) > 1e-15 + 4 * un) return 1;
+    if (std::abs(std::abs(left[0]) - 1) > 1e-15 || std::abs(std::abs(left[1]) - 1) > 1e-15 ||
+        std::abs(std::abs(out[2]) - 1) > 1e-15)
+      return 2;
+  }
+  return 0;
+}
+
+// Along each qubit, the matrices the kernel applies for a phase chain (split gates as R
+// diag(1, ph), the last gate dense) multiply to the gates' own matrices, read from the
+// same circuit planned without the split; no phase is left at the end of the plan.
+static int check_chains(const Plan& p, const Plan& plain, const qsv_circuit& c, const std::vector<double>& params) {
+  std::vector<cplx> t1((size_t)p.ctab_size), t0((size_t)plain.ctab_size);
+  bind_ctab(p, &c, params.data(), nullptr, 0, t1.data());
+  bind_ctab(plain, &c, params.data(), nullptr, 0, t0.data());
+  std::vector<int> own(p.prims.size(), -1);
+  for (const Fill& f : plain.fills)
+    if (f.kind == F_PRIM_MATRIX) own[f.prim] = f.offset;
+  std::vector<cplx> E(4 * (size_t)c.n_qubits), U(4 * (size_t)c.n_qubits);
+  std::vector<char> open(c.n_qubits, 0);
+  auto reset = [&](int q) {
+    for (int i = 0; i < 4; ++i) E[4 * q + i] = U[4 * q + i] = (i == 0 || i == 3) ? 1.0 : 0.0;
+    open[q] = 0;
+  };
+  for (int q = 0; q < c.n_qubits; ++q) reset(q);
+  for (const Fill& f : p.fills) {
+    if (f.kind != F_GATE_CHAIN) continue;
+    const int q = p.prims[f.prim].q0;
+    if (own[f.prim] < 0) return 1;
+    const cplx* g = &t0[own[f.prim]];
+    const cplx* m = &t1[f.offset];
+    cplx k[4];
+    if (f.count) {
+      k[0] = m[0].real();
+      k[1] = m[0].imag() * m[2];
+      k[2] = m[1].real();
+      k[3] = m[1].imag() * m[2];
+      ++g_split_gates;
+    } else {
+      for (int i = 0; i < 4; ++i) k[i] = m[i];
+    }
+    mul2(k, &E[4 * q], &E[4 * q]);
+    mul2(g, &U[4 * q], &U[4 * q]);
+    open[q] = f.count ? 1 : 0;
+    if (!f.count) {
+      for (int i = 0; i < 4; ++i)
+        if (std::abs(E[4 * q + i] - U[4 * q + i]) > 1e-12) return 2;
+      reset(q);
+    }
+  }
+  for (int q = 0; q < c.n_qubits; ++q)
+    if (open[q]) return 3;
+  return 0;
+}
 
 static int check_plan(const Plan& p, const qsv_circuit& c, const std::vector<double>& params, int& checks) {
   std::vector<int> seen(p.prims.size(), 0);
@@ -187,6 +308,10 @@ int main() {
   std::mt19937 rng(2406);
   int bad = 0, checks = 0;
   try {
+    if (const int r = check_split_gate(rng)) {
+      printf("split_gate check %d failed\n", r);
+      bad = 1;
+    }
     for (int trial = 0; trial < 60; ++trial) {
       const int n = 2 + trial % 15;
       Circ k;
@@ -201,7 +326,13 @@ int main() {
             for (bool relayout : {false, true}) {
               PlanOptions o = state_plan_options(dtype, n, tile, tile, adjoint, true, relayout);
               const Plan p = build_plan(&k.c, adjoint, o);
-              const int r = check_plan(p, k.c, params, checks);
+              int r = check_plan(p, k.c, params, checks);
+              if (!r && o.split) {
+                PlanOptions o2 = o;
+                o2.split = false;
+                const int rc = check_chains(p, build_plan(&k.c, adjoint, o2), k.c, params);
+                if (rc) r = 100 + rc;
+              }
               if (r) {
                 printf("trial %d n=%d dtype=%d adjoint=%d tile=%d relayout=%d: check %d failed\n", trial, n, dtype,
                        (int)adjoint, tile, (int)relayout, r);
@@ -269,5 +400,6 @@ int main() {
   }
   printf("plans checked: %d\n", checks);
   printf("unitary fused blocks checked: %d\n", g_unitary_blocks);
-  return bad || checks < 1000 || g_unitary_blocks < 100;
+  printf("split gates checked along their chains: %d\n", g_split_gates);
+  return bad || checks < 1000 || g_unitary_blocks < 100 || g_split_gates < 1000;
 }

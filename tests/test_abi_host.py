@@ -139,3 +139,4 @@ def test_planner_under_sanitizers(tmp_path):
     res = _sanitized_host_program(tmp_path, "planner_fuzz")
     assert res.returncode == 0, res.stdout[-2000:] + res.stderr[-4000:]
     assert "plans checked" in res.stdout and "unitary fused blocks checked" in res.stdout
+    assert "split gates checked along their chains" in res.stdout

@@ -63,6 +63,37 @@ def test_apply_circuit_matches_oracle(Q, dtype, n, tile, seed):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,tile,seed", [(14, None, 41), (16, 9, 42), (15, 11, 43)])
+def test_non_unitary_matrices_match_oracle(Q, dtype, n, tile, seed):
+    """Brick layers whose one-qubit matrices are Haar unitaries, general complex matrices
+    (scaled to spectral norm 1) and unitaries off by 1e-9: only exact unitaries may run as a
+    phase and a real matrix, the others stay dense."""
+    print(f"non-unitary n={n} tile={tile} seed={seed} dtype={dtype}", flush=True)
+    rng = np.random.default_rng(seed)
+    gs = []
+    for layer in range(8):
+        for q in range(n):
+            kind = rng.integers(3)
+            if kind == 0:
+                m = W.haar_unitary_2x2(rng)
+            elif kind == 1:
+                m = rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))
+                m /= np.linalg.norm(m, 2)
+            else:
+                m = W.haar_unitary_2x2(rng) * (1.0 + 1e-9)
+            gs.append(W.gate("MAT1", (q,), matrix=m))
+        for a in range(layer % 2, n - 1, 2):
+            gs.append(W.gate("Z", (a + 1,), ctrls=(a,)))
+    circ = W.circuit(n, gs)
+    psi0 = W.random_state(n, np.random.default_rng(seed + 1000))
+    ref = O.simulate(circ, np.zeros(0), psi0)
+    s = _new_state(Q, n, dtype, psi0.astype(np.complex64 if dtype == "c64" else np.complex128), tile=tile)
+    Q.qsv_apply_circuit(s, circ, np.zeros(0))
+    got = Q.qsv_state_get(s)
+    assert np.max(np.abs(got - ref)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("n,tile,seed", [(20, 9, 31), (19, 10, 32), (21, 11, 33), (18, 9, 34), (22, 12, 35)])
 def test_relayout_passes_match_in_place(Q, dtype, n, tile, seed):
     """Fused passes that store each tile in the next pass's bit layout (alternating between
