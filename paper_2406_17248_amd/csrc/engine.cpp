@@ -240,6 +240,23 @@ int prim_gen(const Prim& p, cplx* out) {
   }
 }
 
+// The structure of a one-qubit primitive's matrix (any angle, dagger or not): real (RY, H,
+// X) or real diagonal with imaginary off-diagonal entries (RX, Y); 0 for general matrices.
+int32_t matrix_form(const Prim& p, const qsv_circuit* c) {
+  if (p.type != P_DENSE1) return 0;
+  switch (p.recipe) {
+    case M_RY_ANGLE: case M_H: return kPlainReal;
+    case M_RX_PLUS: case M_RX_MINUS: return kPlainXlike;
+    case M_GATE:
+      switch (c->gates[p.gate].kind) {
+        case QSV_GATE_RY: case QSV_GATE_H: case QSV_GATE_X: return kPlainReal;
+        case QSV_GATE_RX: case QSV_GATE_Y: return kPlainXlike;
+        default: return 0;
+      }
+    default: return 0;
+  }
+}
+
 int prim_size(const Prim& p) {
   switch (p.type) {
     case P_DENSE1: return 4;
@@ -870,7 +887,7 @@ struct PassEmitter {
         if (p.type == P_DENSE1) op.gkind = p.gen == G_X ? GEN_X : p.gen == G_Y ? GEN_Y : GEN_GENERAL;
       }
       if (reg_index && op.type == OP_DENSE1 && op.lmask == 0)
-        op.plain = (1 + op.a) | (op.b ? kPlainSigns : 0) | (ch == 1 ? kPlainSplit : 0);
+        op.plain = (1 + op.a) | (op.b ? kPlainSigns : 0) | (ch == 1 ? kPlainSplit : ch ? 0 : matrix_form(p, c));
       if (ch && !op.plain) fail(QSV_EINVAL, "internal: phase chain through a decoded gate");
       push(op, prm);
     }

@@ -119,6 +119,37 @@ __device__ __forceinline__ void apply2split(C r0, C r1, C p, C& a0, C& a1) {
   a1.x = fma_s(r1.y, a1.x, p1r);
   a1.y = fma_s(r1.y, a1.y, p1i);
 }
+// Matrix forms of one-qubit gates (bits 5-6 of TileOp::plain): general, split (a phase then
+// a real matrix), real (RY, H, X), and real diagonal with imaginary off-diagonal (RX, Y).
+enum MatForm : int { FORM_GENERAL = 0, FORM_SPLIT = 1, FORM_REAL = 2, FORM_XLIKE = 3 };
+// apply2 for a form: real U (entries' .x) or U = [[a, i b], [i c, d]] (a, d in .x, b, c in .y)
+// in 8 instructions per pair, else the general product
+template <int F, typename C, typename... Pin>
+__device__ __forceinline__ void apply2f(const C* U, C& a0, C& a1, Pin&... pin) {
+  if constexpr (F == FORM_REAL) {
+    auto p0r = U[1].x * a1.x;
+    auto p0i = U[1].x * a1.y;
+    auto p1r = U[2].x * a0.x;
+    auto p1i = U[2].x * a0.y;
+    order(p0r, p0i, p1r, p1i, pin...);
+    a0.x = fma_s(U[0].x, a0.x, p0r);
+    a0.y = fma_s(U[0].x, a0.y, p0i);
+    a1.x = fma_s(U[3].x, a1.x, p1r);
+    a1.y = fma_s(U[3].x, a1.y, p1i);
+  } else if constexpr (F == FORM_XLIKE) {
+    auto p0r = -U[1].y * a1.y;
+    auto p0i = U[1].y * a1.x;
+    auto p1r = -U[2].y * a0.y;
+    auto p1i = U[2].y * a0.x;
+    order(p0r, p0i, p1r, p1i, pin...);
+    a0.x = fma_s(U[0].x, a0.x, p0r);
+    a0.y = fma_s(U[0].x, a0.y, p0i);
+    a1.x = fma_s(U[3].x, a1.x, p1r);
+    a1.y = fma_s(U[3].x, a1.y, p1i);
+  } else {
+    apply2(U[0], U[1], U[2], U[3], a0, a1, pin...);
+  }
+}
 // a <- a * p in place (p per lane), with an optional `pin` as above
 template <typename C, typename... Pin> __device__ __forceinline__ void cmul_in(C& a, C p, Pin&... pin) {
   auto pr = -a.y * p.y;
@@ -559,10 +590,10 @@ __device__ __forceinline__ double grad_term(C w0, C w1, C v0, C v1, const C* G) 
   else return im_conj_mul(w0, cdot2(G[0], v0, G[1], v1)) + im_conj_mul(w1, cdot2(G[2], v0, G[3], v1));
 }
 
-template <int I, int NR, bool ADJ, int GK, typename C, bool SPLIT = false>
+template <int I, int NR, bool ADJ, int GK, typename C, int F = FORM_GENERAL>
 __device__ __forceinline__ void reg1(C* v, C* w, int jt, uint32_t reg, uint32_t lm, const C* U, bool grad,
                                      const C* G, double& acc) {
-  if (SPLIT) {  // forward, uncontrolled
+  if constexpr (F == FORM_SPLIT) {  // forward, uncontrolled
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       if (k & (1 << I)) continue;
@@ -578,11 +609,11 @@ __device__ __forceinline__ void reg1(C* v, C* w, int jt, uint32_t reg, uint32_t 
       if (ADJ) {
         double g = 0.0;
         if (grad) g = grad_term<GK>(w[k], w[k1], v[k], v[k1], G);
-        apply2(U[0], U[1], U[2], U[3], w[k], w[k1], g);
-        apply2(U[0], U[1], U[2], U[3], v[k], v[k1], g);
+        apply2f<F>(U, w[k], w[k1], g);
+        apply2f<F>(U, v[k], v[k1], g);
         acc += g;
       } else {
-        apply2(U[0], U[1], U[2], U[3], v[k], v[k1]);
+        apply2f<F>(U, v[k], v[k1]);
       }
     }
     return;
@@ -620,16 +651,16 @@ __device__ __forceinline__ void mat4(const C* M, const C* x, C* y) {
   }
 }
 
-template <int RB, bool ADJ, int GK, typename C, bool SPLIT = false>
+template <int RB, bool ADJ, int GK, typename C, int F = FORM_GENERAL>
 __device__ __forceinline__ void reg1_slot(int i, C* v, C* w, int jt, uint32_t reg, uint32_t lm, const C* U,
                                           bool grad, const C* G, double& acc) {
   constexpr int NR = 1 << RB;
   switch (i) {
-    case 0: reg1<0, NR, ADJ, GK, C, SPLIT>(v, w, jt, reg, lm, U, grad, G, acc); break;
-    case 1: reg1<1, NR, ADJ, GK, C, SPLIT>(v, w, jt, reg, lm, U, grad, G, acc); break;
-    case 2: reg1<2, NR, ADJ, GK, C, SPLIT>(v, w, jt, reg, lm, U, grad, G, acc); break;
+    case 0: reg1<0, NR, ADJ, GK, C, F>(v, w, jt, reg, lm, U, grad, G, acc); break;
+    case 1: reg1<1, NR, ADJ, GK, C, F>(v, w, jt, reg, lm, U, grad, G, acc); break;
+    case 2: reg1<2, NR, ADJ, GK, C, F>(v, w, jt, reg, lm, U, grad, G, acc); break;
     default:
-      if constexpr (RB > 3) reg1<(RB > 3 ? 3 : 0), NR, ADJ, GK, C, SPLIT>(v, w, jt, reg, lm, U, grad, G, acc);
+      if constexpr (RB > 3) reg1<(RB > 3 ? 3 : 0), NR, ADJ, GK, C, F>(v, w, jt, reg, lm, U, grad, G, acc);
       break;
   }
 }
@@ -928,13 +959,29 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
             if (ADJ) flip_sign(w[k], f);
           }
         }
+        const int form = (plain & kPlainForm) / kPlainSplit;
         if (ADJ && gen >= 0) {
           C G[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) G[r] = ldc(T + gen + r);
-          reg1_dispatch<RB, ADJ>(slot, v, w, jt, reg_cur, 0u, U, true, gkind, G, acc);
-        } else if (!ADJ && (plain & kPlainSplit)) {
-          reg1_slot<RB, ADJ, GEN_GENERAL, C, true>(slot, v, w, jt, reg_cur, 0u, U, false, U, acc);
+          // the generator forms of RX and RY come with their gates' matrix forms
+          if (gkind == GEN_X && form == FORM_XLIKE) {
+            double part = 0.0;
+            reg1_slot<RB, ADJ, GEN_X, C, FORM_XLIKE>(slot, v, w, jt, reg_cur, 0u, U, true, G, part);
+            acc = __builtin_fma((double)G[1].x, part, acc);
+          } else if (gkind == GEN_Y && form == FORM_REAL) {
+            double part = 0.0;
+            reg1_slot<RB, ADJ, GEN_Y, C, FORM_REAL>(slot, v, w, jt, reg_cur, 0u, U, true, G, part);
+            acc = __builtin_fma((double)G[2].y, part, acc);
+          } else {
+            reg1_dispatch<RB, ADJ>(slot, v, w, jt, reg_cur, 0u, U, true, gkind, G, acc);
+          }
+        } else if (!ADJ && form == FORM_SPLIT) {
+          reg1_slot<RB, ADJ, GEN_GENERAL, C, FORM_SPLIT>(slot, v, w, jt, reg_cur, 0u, U, false, U, acc);
+        } else if (form == FORM_REAL) {
+          reg1_slot<RB, ADJ, GEN_GENERAL, C, FORM_REAL>(slot, v, w, jt, reg_cur, 0u, U, false, U, acc);
+        } else if (form == FORM_XLIKE) {
+          reg1_slot<RB, ADJ, GEN_GENERAL, C, FORM_XLIKE>(slot, v, w, jt, reg_cur, 0u, U, false, U, acc);
         } else {
           reg1_slot<RB, ADJ, GEN_GENERAL>(slot, v, w, jt, reg_cur, 0u, U, false, U, acc);
         }

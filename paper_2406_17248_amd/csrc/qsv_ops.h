@@ -46,11 +46,13 @@ constexpr uint32_t kHasOutsideControls = 0x80000000u;
 
 struct TileOp {
   // Register-blocked passes: a one-qubit gate on a register slot without controls,
-  // optionally after a run of sign flips (kPlainSigns), has plain = 1 + slot (| kPlainSigns,
-  // | kPlainSplit when its matrix is given as a phase on the slot's 1 half followed by a
-  // real 2x2 matrix: ctab[mat] = (R00, R01), ctab[mat + 1] = (R10, R11), ctab[mat + 2] = the
-  // phase); a fused block has plain = kPlainBlock | (1 + slot).  The kernel reads the first
-  // eight fields at once and decodes nothing else for these ops.  0 for every other op.
+  // optionally after a run of sign flips (kPlainSigns), has plain = 1 + slot (| kPlainSigns)
+  // | the form of its matrix (kPlainForm bits): kPlainSplit, a phase on the slot's 1 half
+  // then a real 2x2 matrix (ctab[mat] = (R00, R01), ctab[mat + 1] = (R10, R11), ctab[mat + 2]
+  // = the phase); kPlainReal, a real matrix (RY, H, X); kPlainXlike, real diagonal and
+  // imaginary off-diagonal entries (RX, Y); none: a general 2x2.  A fused block has plain =
+  // kPlainBlock | (1 + slot).  The kernel reads the first eight fields at once and decodes
+  // nothing else for these ops.  0 for every other op.
   int32_t  plain;
   int32_t  mat;        // ctab offset of the matrix (DENSE) or phase table (ZZ)
   int32_t  first;      // DIAG / ZZ / sign runs: first entry
@@ -66,7 +68,8 @@ struct TileOp {
   uint32_t lmask;      // controls on local bits, in j-space: apply where (j & lmask) == lmask
   uint64_t omask;      // controls on bits outside the tile: apply iff (base & omask) == omask
 };
-constexpr int32_t kPlainSigns = 8, kPlainBlock = 16, kPlainSplit = 32;
+constexpr int32_t kPlainSigns = 8, kPlainBlock = 16;
+constexpr int32_t kPlainSplit = 32, kPlainReal = 64, kPlainXlike = 96, kPlainForm = 96;
 static_assert(offsetof(TileOp, plain) == 0 && offsetof(TileOp, gkind) == 28 && alignof(TileOp) == 8,
               "plain .. gkind form the record's first 32 bytes");
 // Generator forms of DENSE1 ops (k = the chain-rule factor, read from the generator table):
