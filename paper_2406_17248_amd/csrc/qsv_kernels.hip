@@ -182,9 +182,41 @@ __device__ __forceinline__ uint64_t pdep64(uint64_t v, uint64_t mask) {
   return r;
 }
 
+// The value of a lane chosen by a DPP control (0: where the control selects no lane).
+template <int CTRL> __device__ __forceinline__ double dpp_f64(double x) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+// x + (x of lane l ^ 16) (L = 4) or l ^ 32 (L = 5), when x is equal across the 16 (32) lanes
+// of each row (half-wave): the row (half-wave) swap of two copies leaves one of each pair.
+template <int L> __device__ __forceinline__ double swap_add_f64(double x) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x);
+  uint32_t a0 = (uint32_t)u, b0 = a0, a1 = (uint32_t)(u >> 32), b1 = a1;
+  if constexpr (L == 5) {
+    const auto r0 = __builtin_amdgcn_permlane32_swap(a0, b0, false, false);
+    const auto r1 = __builtin_amdgcn_permlane32_swap(a1, b1, false, false);
+    a0 = r0[0]; b0 = r0[1]; a1 = r1[0]; b1 = r1[1];
+  } else {
+    const auto r0 = __builtin_amdgcn_permlane16_swap(a0, b0, false, false);
+    const auto r1 = __builtin_amdgcn_permlane16_swap(a1, b1, false, false);
+    a0 = r0[0]; b0 = r0[1]; a1 = r1[0]; b1 = r1[1];
+  }
+  return __longlong_as_double((long long)(((uint64_t)a1 << 32) | a0)) +
+         __longlong_as_double((long long)(((uint64_t)b1 << 32) | b0));
+}
+// Sum over the 64 lanes of a wave, returned in every lane (every lane must be active): a
+// butterfly by cross-lane moves that stay out of LDS - quad permutes for lane bits 0 and 1,
+// the half-row and row mirrors for bits 2 and 3 (each quad, then each half-row, already
+// holds one value), the row and half-wave swaps for bits 4 and 5.
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
+  v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]: lane ^ 1
+  v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]: lane ^ 2
+  v += dpp_f64<0x141>(v);  // row_half_mirror: the other quad of the half-row
+  v += dpp_f64<0x140>(v);  // row_mirror: the other half of the row
+  v = swap_add_f64<4>(v);
+  return swap_add_f64<5>(v);
 }
 
 // Read-only tables (op lists, diagonal entries, edges, bound matrices, Pauli terms) are
