@@ -5,8 +5,9 @@
 // types, every tile width from per-gate streaming up to 13 qubits, with and without
 // relayout) and bound; Pauli sums are validated and grouped; invalid circuits must be
 // rejected with QSV_EINVAL / QSV_ERANGE.  The structural facts checked on every plan:
-// every primitive is executed exactly once, each op's table offsets lie inside the bound
-// table, each pass's deposit entries and ops lie inside the plan's arrays, and every
+// each op's table offsets and entry runs (diagonal runs, sign runs riding on gates, ZZ
+// edges) lie inside the bound table and the plan's arrays,
+// each pass's deposit entries and ops lie inside the plan's arrays, and every
 // register layout of a register-blocked pass (load layout, after each LDS remap or
 // cross-lane transposition) is a bijection of the tile's local bits whose transpositions
 // name valid slot and lane bits and lead to the layout the op states, and every fused block's
@@ -253,6 +254,7 @@ static int check_plan(const Plan& p, const qsv_circuit& c, const std::vector<dou
       if ((op.type == OP_DIAG && op.first + op.count > (int)p.diag.size()) ||
           (op.type == OP_ZZ && op.first + op.count > (int)p.edges.size()))
         return 5;
+      if (op.type == OP_DENSE1 && op.b && op.first + op.count > (int)p.diag.size()) return 5;
     }
     for (const DiagEntry& d : p.diag)
       if (d.mat >= p.ctab_size || d.gen >= p.ctab_size) return 6;
