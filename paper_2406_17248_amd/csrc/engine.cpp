@@ -796,12 +796,22 @@ struct PassEmitter {
   int32_t bqs[3] = {0, 0, 0}; // global qubit of block index bits 0..2
   int32_t bslot = -1;
   int32_t open = -1;          // the open block (index in plan.blocks), -1 if none
+  size_t merge_floor = 0;  // ops before this index belong to an earlier round (kept on rollback)
   void close_block() {
     if (open < 0) return;
     TileOp op{};
     op.type = OP_BLOCK;
     op.a = bslot;
     op.plain = kPlainBlock | (1 + bslot);
+    // a sign-only diagonal run right before the block rides on it
+    if (plan.ops.size() > merge_floor && plan.ops.back().type == OP_DIAG && plan.ops.back().b == 0 &&
+        op_param.back() < 0) {
+      op.first = plan.ops.back().first;
+      op.count = plan.ops.back().count;
+      op.plain |= kPlainSigns;
+      plan.ops.pop_back();
+      op_param.pop_back();
+    }
     op.mat = alloc(128);
     op.gen = -1;
     op.pslot = -1;
@@ -994,6 +1004,8 @@ struct PassEmitter {
         ++e;
       }
       op.count = (int32_t)(plan.diag.size() - op.first);
+      // register passes: sign-only runs take the kernel's short path
+      if (rb && op.b == 0 && run_param < 0) op.plain = kPlainSigns;
       push(op, run_param);
       k = e;
     }
@@ -1255,6 +1267,7 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
         const Saved sv{plan.ops.size(), plan.diag.size(), plan.edges.size(), plan.fills.size(),
                        plan.blocks.size(), em.op_param.size(), plan.ctab_size, em.pending,
                        em.pending_touched, em.lay};
+        em.merge_floor = sv.ops;
         if (blockable[ri]) {
           // block round: two of its qubits on lane bits 4 and 5, the third on a slot bit
           const uint32_t tb = need[ri];

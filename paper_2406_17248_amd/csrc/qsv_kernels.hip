@@ -964,11 +964,23 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
     const int gen = (int)(uint32_t)h2, pslot = (int)(h2 >> 32);
     const int flush = (int)(uint32_t)h3, gkind = (int)(h3 >> 32);
     if (plain) {
-      // the short path: a one-qubit gate on a register slot (after its sign run, if any)
-      // or a fused block, nothing else to decode
+      // the short path: a run of sign flips, then a one-qubit gate on a register slot or a
+      // fused block (or nothing), with nothing else to decode
       const int slot = (plain & 7) - 1;
+      auto sign_run = [&]() {
+        uint32_t touched;
+        const uint32_t sm = sign_slots(A.diag + first, count, base, (uint32_t)jt, touched);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          if (!((touched >> k) & 1u)) continue;
+          const uint32_t f = (sm << (31 - k)) & 0x80000000u;
+          flip_sign(v[k], f);
+          if (ADJ) flip_sign(w[k], f);
+        }
+      };
       if (!ADJ && (plain & kPlainBlock)) {
         if (active) {
+          if (plain & kPlainSigns) sign_run();
           // the lane's four A operands: 4 consecutive reals at 4 * lane of the block's table
           const R* ap = reinterpret_cast<const R*>(T + mat) + 4 * (tid & 63);
           R am[4];
@@ -976,21 +988,13 @@ __device__ __forceinline__ void rb_body(const PassArgs& A, const uint64_t tile, 
           for (int j = 0; j < 4; ++j) am[j] = ap[j];
           block_dispatch<RB>(slot, v, am);
         }
+      } else if (slot < 0) {
+        if (active) sign_run();
       } else if (active) {
         C U[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) U[r] = ldc(T + mat + r);
-        if (plain & kPlainSigns) {
-          uint32_t touched;
-          const uint32_t sm = sign_slots(A.diag + first, count, base, (uint32_t)jt, touched);
-#pragma unroll
-          for (int k = 0; k < NR; ++k) {
-            if (!((touched >> k) & 1u)) continue;
-            const uint32_t f = (sm << (31 - k)) & 0x80000000u;
-            flip_sign(v[k], f);
-            if (ADJ) flip_sign(w[k], f);
-          }
-        }
+        if (plain & kPlainSigns) sign_run();
         const int form = (plain & kPlainForm) / kPlainSplit;
         if (ADJ && gen >= 0) {
           C G[4];

@@ -45,14 +45,15 @@ enum OpType : int32_t {
 constexpr uint32_t kHasOutsideControls = 0x80000000u;
 
 struct TileOp {
-  // Register-blocked passes: a one-qubit gate on a register slot without controls,
-  // optionally after a run of sign flips (kPlainSigns), has plain = 1 + slot (| kPlainSigns)
+  // Register-blocked passes: a run of sign flips alone has plain = kPlainSigns.  A one-qubit
+  // gate on a register slot without controls, optionally after a run of sign flips
+  // (kPlainSigns), has plain = 1 + slot (| kPlainSigns)
   // | the form of its matrix (kPlainForm bits): kPlainSplit, a phase on the slot's 1 half
   // then a real 2x2 matrix (ctab[mat] = (R00, R01), ctab[mat + 1] = (R10, R11), ctab[mat + 2]
   // = the phase); kPlainReal, a real matrix (RY, H, X); kPlainXlike, real diagonal and
   // imaginary off-diagonal entries (RX, Y); none: a general 2x2.  A fused block has plain =
-  // kPlainBlock | (1 + slot).  The kernel reads the first eight fields at once and decodes
-  // nothing else for these ops.  0 for every other op.
+  // kPlainBlock | (1 + slot) (| kPlainSigns).  The kernel reads the first eight fields at once
+  // and decodes nothing else for these ops.  0 for every other op.
   int32_t  plain;
   int32_t  mat;        // ctab offset of the matrix (DENSE) or phase table (ZZ)
   int32_t  first;      // DIAG / ZZ / sign runs: first entry

@@ -254,7 +254,8 @@ static int check_plan(const Plan& p, const qsv_circuit& c, const std::vector<dou
       if ((op.type == OP_DIAG && op.first + op.count > (int)p.diag.size()) ||
           (op.type == OP_ZZ && op.first + op.count > (int)p.edges.size()))
         return 5;
-      if (op.type == OP_DENSE1 && op.b && op.first + op.count > (int)p.diag.size()) return 5;
+      if (((op.type == OP_DENSE1 && op.b) || (op.plain & kPlainSigns)) && op.first + op.count > (int)p.diag.size())
+        return 5;
     }
     for (const DiagEntry& d : p.diag)
       if (d.mat >= p.ctab_size || d.gen >= p.ctab_size) return 6;
