@@ -226,13 +226,13 @@ def hea10_leg(Q, reps):
 def batch_leg(Q, reps=5):
     """512 uneven circuits (8-20 qubits, depth 2-10, 50 Pauli strings each), complex64:
     energy and adjoint gradient of every circuit from one HIP-graph replay, after the
-    autotuner picks the tile width; compared with the same circuits one call at a time."""
+    autotuner picks the tile width and schedule; compared with the same circuits one call at a time."""
     import numpy as np
 
     import workloads as W
     circs, hams, params = W.uneven_batch_workload()
     b = Q.qsv_batch_create(circs, hams, "c64")
-    tile = Q.qsv_batch_autotune(b, params)
+    tile, low = Q.qsv_batch_autotune(b, params, with_schedule=True)
     Q.qsv_batch_expectation_and_grad(b, params)
     t0 = time.perf_counter()
     for _ in range(reps):
@@ -253,6 +253,7 @@ def batch_leg(Q, reps=5):
     t_single = time.perf_counter() - t0
     del states, b
     return {"workload": "uneven512_hea_n8-20_depth2-10_50terms", "dtype": "c64", "autotuned_tile": tile,
+            "autotuned_low_qubits": low,
             "circuits_per_s": len(circs) / t_batch, "ms_per_batch": t_batch * 1e3, "graph_replay_device_ms": dev_ms,
             "one_call_per_circuit_ms": t_single * 1e3, "speedup_vs_one_call_per_circuit": t_single / t_batch,
             "max_energy_diff_vs_one_call": worst}

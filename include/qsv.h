@@ -286,9 +286,11 @@ int qsv_batch_info(const qsv_batch* b, size_t* total_params, int64_t* param_offs
                    int32_t* tile_qubits);
 /* Fix the tile (fusion) width of every fused pass, in [9, 13]; rebuilds plans and graph. */
 int qsv_batch_set_tile(qsv_batch* b, int32_t tile_qubits);
-/* Autotuner: time the whole evaluation at each candidate tile width (10..13) with these
- * parameters on the device, keep the fastest, return it in *out_tile. */
-int qsv_batch_autotune(qsv_batch* b, const double* params, int32_t* out_tile);
+/* Autotuner: time the whole evaluation with these parameters on the device for each tile
+ * width (10..13) and tile schedule (2, 3 or 4 low qubits kept by every tile for dense global
+ * accesses: fewer mean fewer passes), keep the fastest and return its width in *out_tile and
+ * its low-qubit count in *out_low_qubits (either may be NULL).  Rebuilds plans and graph. */
+int qsv_batch_autotune(qsv_batch* b, const double* params, int32_t* out_tile, int32_t* out_low_qubits);
 /* out_E[i] = <H_i> of circuit i; out_grad (may be NULL) has the layout of params. */
 int qsv_batch_expectation_and_grad(qsv_batch* b, const double* params, double* out_E, double* out_grad);
 

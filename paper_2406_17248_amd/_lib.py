@@ -132,7 +132,7 @@ def lib():
             "qsv_batch_destroy": ([vp], C.c_int),
             "qsv_batch_info": ([vp, C.POINTER(sz), C.POINTER(i64), dp, C.POINTER(i32)], C.c_int),
             "qsv_batch_set_tile": ([vp, i32], C.c_int),
-            "qsv_batch_autotune": ([vp, dp, C.POINTER(i32)], C.c_int),
+            "qsv_batch_autotune": ([vp, dp, C.POINTER(i32), C.POINTER(i32)], C.c_int),
             "qsv_batch_expectation_and_grad": ([vp, dp, dp, dp], C.c_int),
             "qsv_mpnn_create": ([C.POINTER(C.c_float), C.POINTER(vp)], C.c_int),
             "qsv_mpnn_destroy": ([vp], C.c_int),
@@ -524,11 +524,12 @@ def qsv_batch_set_tile(b, tile_qubits):
     check(lib().qsv_batch_set_tile(b.handle, int(tile_qubits)))
 
 
-def qsv_batch_autotune(b, params):
+def qsv_batch_autotune(b, params, with_schedule=False):
+    """The fastest tile width (and, with_schedule, (width, low qubits kept per tile))."""
     p = np.ascontiguousarray(params, dtype=np.float64)
-    t = C.c_int32()
-    check(lib().qsv_batch_autotune(b.handle, _dp(p), C.byref(t)))
-    return t.value
+    t, low = C.c_int32(), C.c_int32()
+    check(lib().qsv_batch_autotune(b.handle, _dp(p), C.byref(t), C.byref(low)))
+    return (t.value, low.value) if with_schedule else t.value
 
 
 def qsv_batch_expectation_and_grad(b, params):

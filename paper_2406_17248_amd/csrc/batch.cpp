@@ -57,6 +57,7 @@ struct qsv_batch {
   std::vector<HamCopy> ham;
   std::vector<int64_t> param_off;  // n + 1
   int32_t tile = 12;
+  int32_t low = 0;  // qubits every tile keeps (0: 4 for complex64, 3 for complex128)
   double last_ms = 0.0;
   // built configuration
   bool built = false;
@@ -104,7 +105,7 @@ void build(qsv_batch* b) {
   PlanOptions of, oa;
   of.tile_qubits = b->tile;
   oa.tile_qubits = std::min<int>(b->tile, b->dtype == QSV_C64 ? 13 : 12);
-  of.low_qubits = oa.low_qubits = b->dtype == QSV_C64 ? 4 : 3;
+  of.low_qubits = oa.low_qubits = b->low > 0 ? b->low : (b->dtype == QSV_C64 ? 4 : 3);
   of.dtype = oa.dtype = b->dtype;
   of.rb_min = oa.rb_min = 4;  // every pass register-blocked, small tiles with idle threads
   b->fwd.clear();
@@ -518,33 +519,39 @@ int qsv_batch_expectation_and_grad(qsv_batch* b, const double* params, double* o
   });
 }
 
-int qsv_batch_autotune(qsv_batch* b, const double* params, int32_t* out_tile) {
+int qsv_batch_autotune(qsv_batch* b, const double* params, int32_t* out_tile, int32_t* out_low_qubits) {
   return guarded([&] {
     check_batch(b);
     if (b->param_off.back() && !params) raise(QSV_EINVAL, "params is NULL");
     hip_check(hipSetDevice(b->device), "hipSetDevice");
-    const int cands[] = {10, 11, 12, 13};
-    int best = b->tile;
+    // the fusion width and the tile schedule: how many low qubits every tile keeps (dense
+    // global accesses) against how many passes the circuits then need
+    const int tiles[] = {10, 11, 12, 13}, lows[] = {2, 3, 4};
+    int best_t = b->tile, best_l = b->low;
     double best_ms = 1e300;
     std::vector<double> E(b->circ.size());
-    for (int t : cands) {
-      if (b->dtype == QSV_C128 && t > 13) continue;
-      b->tile = t;
-      build(b);
-      evaluate(b, params, E.data(), nullptr);  // warm
-      double ms = 1e300;
-      for (int r = 0; r < 2; ++r) {
-        evaluate(b, params, E.data(), nullptr);
-        ms = std::min(ms, b->last_ms);
+    for (int t : tiles)
+      for (int l : lows) {
+        b->tile = t;
+        b->low = l;
+        build(b);
+        evaluate(b, params, E.data(), nullptr);  // warm
+        double ms = 1e300;
+        for (int r = 0; r < 2; ++r) {
+          evaluate(b, params, E.data(), nullptr);
+          ms = std::min(ms, b->last_ms);
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_t = t;
+          best_l = l;
+        }
       }
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = t;
-      }
-    }
-    b->tile = best;
+    b->tile = best_t;
+    b->low = best_l;
     build(b);
-    if (out_tile) *out_tile = best;
+    if (out_tile) *out_tile = best_t;
+    if (out_low_qubits) *out_low_qubits = best_l;
   });
 }
 

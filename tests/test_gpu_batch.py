@@ -66,8 +66,8 @@ def test_autotune_picks_a_candidate_and_keeps_results(Q):
     circs, hams, params = _small_batch(7)
     b = Q.qsv_batch_create(circs, hams, "c64")
     E0, g0 = Q.qsv_batch_expectation_and_grad(b, params)
-    t = Q.qsv_batch_autotune(b, params)
-    assert t in (10, 11, 12, 13)
+    t, low = Q.qsv_batch_autotune(b, params, with_schedule=True)
+    assert t in (10, 11, 12, 13) and low in (2, 3, 4)
     assert b.info()["tile_qubits"] == t
     E1, g1 = Q.qsv_batch_expectation_and_grad(b, params)
     S = max(_scale(h) for h in hams)
