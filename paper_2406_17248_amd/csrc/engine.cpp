@@ -1115,9 +1115,11 @@ Plan build_plan(const qsv_circuit* c, bool adjoint, const PlanOptions& opt) {
   // dense.
   std::vector<char> chain(plan.prims.size(), 0);
   if (rb && opt.split && !adjoint && !opt.blocks) {
+    // (gates with real or X-like matrices cost 8 instructions per pair as they are, fewer
+    // than a split gate's 12, so they neither join nor extend chains)
     auto splittable = [&](int32_t i) {
       const Prim& pr = plan.prims[i];
-      if (pr.type != P_DENSE1 || pr.cmask != 0) return false;
+      if (pr.type != P_DENSE1 || pr.cmask != 0 || matrix_form(pr, c) != 0) return false;
       const qsv_gate& g = c->gates[pr.gate];
       return pr.recipe != M_GATE || g.kind != QSV_GATE_MAT1 || mat1_is_unitary(c, g);
     };

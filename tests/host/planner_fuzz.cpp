@@ -14,9 +14,10 @@
 // matrix-core operands decode to the real form of a complex matrix, unitary when its gates
 // are (every kind but the explicit matrices, which this fuzzer draws at random, a third of
 // them unitary).  One-qubit gates split into a phase and a real matrix (complex128 forward
-// plans): split_gate reproduces random and edge-case unitaries, and along each qubit the
-// product of what the kernel applies (split gates, then the chain's dense last gate) equals
-// the product of the gates' own matrices.
+// plans, on the random circuits and on brick-like circuits of general one-qubit gates):
+// split_gate reproduces random and edge-case unitaries, and along each qubit the product of
+// what the kernel applies (split gates, then the chain's dense last gate) equals the product
+// of the gates' own matrices.
 // Exit status 0 when every check holds.
 #include <algorithm>
 #include <cmath>
@@ -314,6 +315,62 @@ int main() {
     if (const int r = check_split_gate(rng)) {
       printf("split_gate check %d failed\n", r);
       bad = 1;
+    }
+    // brick-like circuits of general one-qubit gates (unitary matrices and U3) between CZ
+    // layers: long phase chains, across rounds and passes
+    for (int trial = 0; trial < 12; ++trial) {
+      const int n = 9 + trial % 6;
+      Circ k;
+      std::uniform_real_distribution<double> ang(-3.0, 3.0);
+      for (int layer = 0; layer < 6; ++layer) {
+        for (int q = 0; q < n; ++q) {
+          qsv_gate g{};
+          for (int a = 0; a < 3; ++a) g.param_index[a] = -1;
+          g.targets[0] = q;
+          g.targets[1] = -1;
+          g.matrix_offset = -1;
+          if ((q + layer + trial) % 3 == 0) {
+            g.kind = QSV_GATE_U3;
+            for (int a = 0; a < 3; ++a) g.angle_const[a] = ang(rng);
+          } else {
+            g.kind = QSV_GATE_MAT1;
+            g.matrix_offset = (int64_t)(k.mats.size() / 2);
+            cplx h[4];
+            random_unitary(rng, h);
+            for (const cplx& z : h) {
+              k.mats.push_back(z.real());
+              k.mats.push_back(z.imag());
+            }
+          }
+          k.gates.push_back(g);
+        }
+        for (int a = layer % 2; a + 1 < n; a += 2) {
+          qsv_gate g{};
+          for (int b = 0; b < 3; ++b) g.param_index[b] = -1;
+          g.kind = QSV_GATE_Z;
+          g.targets[0] = a + 1;
+          g.targets[1] = -1;
+          g.ctrl_mask = 1ull << a;
+          g.matrix_offset = -1;
+          k.gates.push_back(g);
+        }
+      }
+      k.c = qsv_circuit{n, 0, k.gates.data(), k.gates.size(), k.mats.data(), k.mats.size()};
+      validate_circuit(&k.c, 0, n);
+      for (int tile : {9, 10, 11, 12})
+        for (bool relayout : {false, true}) {
+          PlanOptions o = state_plan_options(QSV_C128, n, tile, tile, false, true, relayout);
+          const Plan p = build_plan(&k.c, false, o);
+          PlanOptions o2 = o;
+          o2.split = false;
+          const std::vector<double> none;
+          int r = check_plan(p, k.c, none, checks);
+          if (!r) r = check_chains(p, build_plan(&k.c, false, o2), k.c, none);
+          if (r) {
+            printf("brick trial %d n=%d tile=%d relayout=%d: check %d failed\n", trial, n, tile, (int)relayout, r);
+            bad = 1;
+          }
+        }
     }
     for (int trial = 0; trial < 60; ++trial) {
       const int n = 2 + trial % 15;
