@@ -1390,7 +1390,13 @@ __device__ __forceinline__ void group_factor(const PauliGroupArgs& A, uint64_t x
   }
 }
 
-template <typename R>
+// One instantiation per way of walking the group (the host picks it from the group's
+// shape), so that each path is allocated registers for itself alone.  Pattern modes (0-3):
+// bit 0 the term table staged in LDS once per workgroup, bit 1 lambda written.
+enum PauliMode { PG_STAGED = 1, PG_LAM = 2, PG_QUAD = 4, PG_DIAG = 5, PG_XMASK = 6 };
+constexpr int kPauliStageTerms = 512;
+
+template <typename R, int MODE>
 __global__ __launch_bounds__(256) void pauli_group(PauliGroupArgs A) {
   using C = typename CT<R>::T;
   __shared__ double red[2][4];
@@ -1399,49 +1405,62 @@ __global__ __launch_bounds__(256) void pauli_group(PauliGroupArgs A) {
   const uint64_t N = 1ull << A.n_qubits;
   const uint64_t stride = (uint64_t)gridDim.x * 256;
   double er = 0.0, ei = 0.0;
-  if (A.xmask == 0 && A.n_pats > 0) {
-    // Diagonal group, in chunks of 4096 consecutive amplitudes x = hi | i << 8 | t (t the
-    // thread, i = 0..15 its slot).  A term's sign splits into a per-chunk part on hi and a
-    // part on the 12 low bits, so per chunk the coefficient of each low pattern p is
-    // C_p = sum_k c_k (-1)^{popcount(hi & z_k)} over the terms with that pattern; a thread
-    // folds its own bits into E_r = sum over patterns with bits 8-11 equal to r of
-    // C_p (-1)^{popcount(t & p)}, and a 16-point Walsh-Hadamard transform gives
-    // f(x) = sum_r E_r (-1)^{popcount(i & r)} for its 16 slots.  Each term costs a few
+  if constexpr (MODE < PG_QUAD) {
+    // Diagonal group with real coefficients, in chunks of 4096 consecutive amplitudes
+    // x = hi | i << 8 | t (t the thread, i = 0..15 its slot).  A term's sign splits into a
+    // per-chunk part on hi and a part on the 12 low bits, so per chunk the coefficient of
+    // each low pattern p is C_p = sum_k c_k (-1)^{popcount(hi & z_k)} over the terms with
+    // that pattern; a thread folds its own bits into E_r = sum over patterns with bits 8-11
+    // equal to r of C_p (-1)^{popcount(t & p)}, and a 16-point Walsh-Hadamard transform
+    // gives f(x) = sum_r E_r (-1)^{popcount(i & r)} for its 16 slots.  Each term costs a few
     // operations per chunk instead of per amplitude, which leaves the pass bound by HBM.
-    __shared__ double cpr[kPauliMaxPatterns], cpi[kPauliMaxPatterns];
+    // With the term table in LDS the per-chunk sums wait only on LDS, so the chunk's
+    // amplitude loads, issued first, stay in flight meanwhile.
+    __shared__ double cp[kPauliMaxPatterns];
+    constexpr bool staged = (MODE & PG_STAGED) != 0, with_lam = (MODE & PG_LAM) != 0;
     const int P = A.n_pats;
-    const bool real_c = A.real_coeffs;
     const int tid = threadIdx.x;
+    const uint64_t* tz = A.zmasks;
+    const double* tc = A.cre;
+    if constexpr (staged) {
+      __shared__ uint64_t sz[kPauliStageTerms];
+      __shared__ double sc[kPauliStageTerms];
+      for (int k = tid; k < A.n_terms; k += 256) {
+        sz[k] = A.zmasks[k];
+        sc[k] = A.cre[k];
+      }
+      tz = sz;
+      tc = sc;
+    }
     const uint64_t n_chunks = N >> 12;
     for (uint64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
       const uint64_t hi = ch << 12;
-      __syncthreads();  // the previous chunk's readers of cpr / cpi are done
+      C v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = psi[hi | (uint64_t)(i << 8) | (uint64_t)tid];
+      __syncthreads();  // the previous chunk's readers of cp are done (and the staging)
       for (int p = tid; p < P; p += 256) {
         const int k0 = (int)(A.pats[p] >> 12);
         const int k1 = p + 1 < P ? (int)(A.pats[p + 1] >> 12) : A.n_terms;
-        double sr = 0.0, si = 0.0;
+        double sr = 0.0;
         for (int k = k0; k < k1; ++k) {
-          const bool neg = __popcll(hi & A.zmasks[k]) & 1;
-          sr += neg ? -A.cre[k] : A.cre[k];
-          if (!real_c) si += neg ? -A.cim[k] : A.cim[k];
+          const bool neg = __popcll(hi & tz[k]) & 1;
+          sr += neg ? -tc[k] : tc[k];
         }
-        cpr[p] = sr;
-        cpi[p] = si;
+        cp[p] = sr;
       }
       __syncthreads();
-      double fr[16], fi[16];
+      double f[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        double a = 0.0, b = 0.0;
+        double a = 0.0;
         const int p0 = ld(A.rfirst + r), p1 = ld(A.rfirst + r + 1);
         for (int p = p0; p < p1; ++p) {
           const uint32_t pat = ld(A.pats + p) & 0xFFu;
           const bool neg = __popc((uint32_t)tid & pat) & 1;
-          a += neg ? -cpr[p] : cpr[p];
-          if (!real_c) b += neg ? -cpi[p] : cpi[p];
+          a += neg ? -cp[p] : cp[p];
         }
-        fr[r] = a;
-        fi[r] = b;
+        f[r] = a;
       }
       // Walsh-Hadamard transform over the 4 slot bits
 #pragma unroll
@@ -1449,35 +1468,25 @@ __global__ __launch_bounds__(256) void pauli_group(PauliGroupArgs A) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           if (r & h) continue;
-          const double a = fr[r], b = fr[r | h];
-          fr[r] = a + b;
-          fr[r | h] = a - b;
-          if (!real_c) {
-            const double c2 = fi[r], d = fi[r | h];
-            fi[r] = c2 + d;
-            fi[r | h] = c2 - d;
-          }
+          const double a = f[r], b = f[r | h];
+          f[r] = a + b;
+          f[r | h] = a - b;
         }
       }
-      C v[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = psi[hi | (uint64_t)(i << 8) | (uint64_t)tid];
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        const double pi = (double)v[i].x * v[i].x + (double)v[i].y * v[i].y;
-        er += pi * fr[i];
-        ei += pi * fi[i];
-        if (lam) {
+        er += ((double)v[i].x * v[i].x + (double)v[i].y * v[i].y) * f[i];
+        if constexpr (with_lam) {
           const uint64_t x = hi | (uint64_t)(i << 8) | (uint64_t)tid;
           C o;
-          o.x = (R)(fr[i] * v[i].x - fi[i] * v[i].y);
-          o.y = (R)(fr[i] * v[i].y + fi[i] * v[i].x);
+          o.x = (R)(f[i] * v[i].x);
+          o.y = (R)(f[i] * v[i].y);
           if (A.accumulate) { const C l = lam[x]; o.x += l.x; o.y += l.y; }
           lam[x] = o;
         }
       }
     }
-  } else if (A.xmask == 0 && A.n_qubits >= 2) {
+  } else if constexpr (MODE == PG_QUAD) {
     // Diagonal group, four consecutive amplitudes per thread: a term's sign parity on the
     // shared high bits is computed once; the two low bits flip it by the uniform pattern
     // pat(z) (bit j set when popcount(j & z) is odd).
@@ -1517,7 +1526,7 @@ __global__ __launch_bounds__(256) void pauli_group(PauliGroupArgs A) {
         }
       }
     }
-  } else if (A.xmask == 0) {
+  } else if constexpr (MODE == PG_DIAG) {
     for (uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x; x < N; x += stride) {
       double fr, fi;
       group_factor<R>(A, x, fr, fi);
@@ -1534,6 +1543,7 @@ __global__ __launch_bounds__(256) void pauli_group(PauliGroupArgs A) {
       }
     }
   } else {
+    static_assert(MODE == PG_XMASK, "unknown Pauli pass mode");
     const int h = 63 - __clzll(A.xmask);
     const uint64_t lowm = (1ull << h) - 1;
     for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < (N >> 1); p += stride) {
@@ -1921,10 +1931,26 @@ unsigned pauli_blocks(int n) {
   return stream_blocks(work) < 2048 ? stream_blocks(work) : 2048;
 }
 
+template <typename R>
+void launch_pauli_mode(const PauliGroupArgs& A, dim3 grid, hipStream_t s) {
+  if (A.xmask != 0) {
+    pauli_group<R, PG_XMASK><<<grid, 256, 0, s>>>(A);
+  } else if (A.n_pats > 0 && A.real_coeffs) {
+    const int m = (A.n_terms <= kPauliStageTerms ? PG_STAGED : 0) | (A.lam ? PG_LAM : 0);
+    switch (m) {
+      case 0: pauli_group<R, 0><<<grid, 256, 0, s>>>(A); break;
+      case 1: pauli_group<R, 1><<<grid, 256, 0, s>>>(A); break;
+      case 2: pauli_group<R, 2><<<grid, 256, 0, s>>>(A); break;
+      default: pauli_group<R, 3><<<grid, 256, 0, s>>>(A); break;
+    }
+  } else if (A.n_qubits >= 2) pauli_group<R, PG_QUAD><<<grid, 256, 0, s>>>(A);
+  else pauli_group<R, PG_DIAG><<<grid, 256, 0, s>>>(A);
+}
+
 hipError_t launch_pauli_group(int dtype, const PauliGroupArgs& A, int batch, hipStream_t s) {
   const dim3 grid(pauli_blocks(A.n_qubits), (unsigned)batch);
-  if (dtype == 0) pauli_group<float><<<grid, 256, 0, s>>>(A);
-  else pauli_group<double><<<grid, 256, 0, s>>>(A);
+  if (dtype == 0) launch_pauli_mode<float>(A, grid, s);
+  else launch_pauli_mode<double>(A, grid, s);
   return hipGetLastError();
 }
 

@@ -197,7 +197,9 @@ struct PauliGroupArgs {
   int32_t      real_coeffs;   // 1 when every cim is 0 (the imaginary part is not accumulated)
   // Diagonal groups over n >= 12 qubits (n_pats > 0): the terms sorted by their pattern on
   // the 12 low qubits; pats[p] = pattern | (index of its first term) << 12, and the patterns
-  // whose bits 8-11 equal r are pats[rfirst[r] .. rfirst[r + 1]) (r = 0..15).
+  // whose bits 8-11 equal r are pats[rfirst[r] .. rfirst[r + 1]) (r = 0..15).  The pass
+  // walks such a group by pattern when its coefficients are real (always, for the real
+  // coefficients the ABI takes), with the term table in LDS up to 512 terms.
   const uint32_t* pats;
   const int32_t*  rfirst;
   int32_t      n_pats;

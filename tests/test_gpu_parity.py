@@ -172,6 +172,37 @@ def test_expectation_and_hpsi_match_oracle(Q, dtype, n, seed):
     assert np.array_equal(Q.qsv_state_get(s), psi.astype(npdt))  # get_* leaves the state unchanged
 
 
+def _diagonal_sum(n, n_terms, n_low_patterns, rng):
+    """Z-strings whose parts on the 12 low qubits come from a few patterns: the diagonal
+    pass evaluates them pattern by pattern (terms sorted by pattern, chunks of 2^12)."""
+    lows = [0] + [int(m) for m in rng.integers(1, 1 << 12, n_low_patterns - 1)]
+    terms = [(float(rng.standard_normal()), ())]
+    for _ in range(n_terms):
+        z = int(rng.choice(lows)) | int(rng.integers(0, 1 << (n - 12))) << 12
+        terms.append((float(rng.standard_normal()), tuple((q, "Z") for q in range(n) if z >> q & 1)))
+    return terms
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,n_terms,n_pats,seed", [(12, 40, 9, 1), (14, 300, 60, 2), (14, 700, 200, 3),
+                                                   (13, 513, 255, 4)])
+def test_diagonal_sums_match_oracle(Q, dtype, n, n_terms, n_pats, seed):
+    """Diagonal Hamiltonians with term tables below and above the workgroup staging limit
+    (512 terms), expectation only and with H psi written."""
+    print(f"diagonal sum n={n} terms={n_terms} dtype={dtype}", flush=True)
+    rng = np.random.default_rng(seed)
+    terms = _diagonal_sum(n, n_terms, n_pats, rng)
+    psi = W.random_state(n, rng)
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    s = _new_state(Q, n, dtype, psi.astype(npdt))
+    psi_used = psi.astype(npdt).astype(np.complex128)
+    tol = TOL[dtype] * _scale(terms)
+    assert abs(Q.qsv_expectation(s, terms) - O.expectation(psi_used, n, terms)) <= tol
+    d = Q.qsv_state_create(n, dtype)
+    Q.qsv_apply_pauli_sum(d, s, terms)
+    assert np.max(np.abs(Q.qsv_state_get(d) - O.apply_pauli_sum(psi_used, n, terms))) <= tol
+
+
 # ------------------------------------------------------------------------------------------
 # gradients
 # ------------------------------------------------------------------------------------------
