@@ -1601,7 +1601,10 @@ template <typename R>
 __global__ __launch_bounds__(256) void set_basis(void* psi_, int64_t bstride, uint64_t N, uint64_t index) {
   using C = typename CT<R>::T;
   C* psi = reinterpret_cast<C*>(psi_) + (int64_t)blockIdx.y * bstride;
-  for (uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x; x < N; x += (uint64_t)gridDim.x * 256) {
+  // each workgroup writes one contiguous range
+  const uint64_t per = (N + gridDim.x - 1) / gridDim.x;
+  const uint64_t x0 = (uint64_t)blockIdx.x * per, x1 = x0 + per < N ? x0 + per : N;
+  for (uint64_t x = x0 + threadIdx.x; x < x1; x += 256) {
     C v;
     v.x = (x == index) ? (R)1 : (R)0;
     v.y = (R)0;
