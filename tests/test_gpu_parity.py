@@ -186,12 +186,16 @@ def _diagonal_sum(n, n_terms, n_low_patterns, rng):
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("n,n_terms,n_pats,seed", [(12, 40, 9, 1), (14, 300, 60, 2), (14, 700, 200, 3),
                                                    (13, 513, 255, 4)])
-def test_diagonal_sums_match_oracle(Q, dtype, n, n_terms, n_pats, seed):
+@pytest.mark.parametrize("lead", [False, True])
+def test_diagonal_sums_match_oracle(Q, dtype, n, n_terms, n_pats, seed, lead):
     """Diagonal Hamiltonians with term tables below and above the workgroup staging limit
-    (512 terms), expectation only and with H psi written."""
-    print(f"diagonal sum n={n} terms={n_terms} dtype={dtype}", flush=True)
+    (512 terms), expectation only and with H psi written; with `lead` an X/Y term comes
+    first, so the diagonal group adds its H psi to that of the group before it."""
+    print(f"diagonal sum n={n} terms={n_terms} lead={lead} dtype={dtype}", flush=True)
     rng = np.random.default_rng(seed)
     terms = _diagonal_sum(n, n_terms, n_pats, rng)
+    if lead:
+        terms = [(0.7, ((3, "X"), (n - 1, "Y")))] + terms
     psi = W.random_state(n, rng)
     npdt = np.complex64 if dtype == "c64" else np.complex128
     s = _new_state(Q, n, dtype, psi.astype(npdt))
